@@ -1,0 +1,188 @@
+"""Pins of the oracle's full time step against properties the paper and the
+mathematics fix (arXiv:2012.14729).
+
+* brute-force per-cell loops (independent code) agree on 8x8 grids for every
+  force form and boundary set-up;
+* the order parameter is conserved (Sec. IV: the wall condition of Eq. 44
+  conserves mass; the CH forcing of Eq. 36 has zero sum);
+* a uniform fluid at rest stays exactly at rest;
+* integer translations and the x<->y transposition commute with the step;
+* plane Couette and Poiseuille flows between half-way bounce-back walls
+  (Eq. 43) are reproduced exactly;
+* a flat tanh interface (Eq. 4) is stationary;
+* a droplet obeys the Laplace law dp = sigma/R (Sec. V.A, Table I band).
+"""
+import math
+
+import pytest
+import torch
+
+from oracle import lbm_ref as R
+from oracle.brute import Brute
+
+torch.set_default_dtype(torch.float64)
+
+BCS = [  # wall_x, wall_y, u_lo, u_hi, gx, gy
+    (0, 0, 0.0, 0.0, 0.0, 0.0),
+    (0, 1, -0.01, 0.02, 0.0, 0.0),
+    (1, 0, 0.01, 0.0, 0.0, -1e-4),
+    (1, 1, 0.0, 0.0, 1e-4, 0.0),
+]
+
+
+def drop(nx, ny, r, w, xc, yc):
+    y, x = torch.meshgrid(torch.arange(ny, dtype=torch.float64), torch.arange(nx, dtype=torch.float64), indexing="ij")
+    return torch.tanh(2 * (r - torch.sqrt((x - xc) ** 2 + (y - yc) ** 2)) / w)
+
+
+@pytest.mark.parametrize("form", R.FORMS)
+@pytest.mark.parametrize("bc", BCS)
+def test_brute_force_agrees(form, bc):
+    wx, wy, ulo, uhi, gx, gy = bc
+    p = R.Params(nx=8, ny=8, wall_x=wx, wall_y=wy, u_wall_lo=ulo, u_wall_hi=uhi, rho1=3.0, rho2=1.0, nu1=0.1,
+                 nu2=0.2, sigma=0.01, W=3.0, M=0.05, tau_h=0.9, gx=gx, gy=gy)
+    phi0 = drop(8, 8, 2.5, 3.0, 3.7, 4.2)
+    g = torch.Generator().manual_seed(7)
+    ux0, uy0 = 1e-3 * torch.randn(8, 8, generator=g), 1e-3 * torch.randn(8, 8, generator=g)
+    st = R.init(p, phi0, ux0, uy0)
+    b = Brute(8, 8, wx, wy, ulo, uhi, 3.0, 1.0, 0.1, 0.2, 0.01, 3.0, 0.05, 0.9, gx, gy)
+    f, h, J = b.init(phi0.tolist(), ux0.tolist(), uy0.tolist())
+    for _ in range(3):
+        st = R.step(st, form, p)
+        f, h, J = b.step(f, h, J, form)
+    assert float((st["f"] - torch.tensor(f)).abs().max()) < 1e-14
+    assert float((st["h"] - torch.tensor(h)).abs().max()) < 1e-14
+    assert float((st["J"] - torch.tensor(J)).abs().max()) < 1e-14
+    mb = b.moments(f, h, form)
+    mo = R.moments(st, form, p)
+    for k in ("phi", "rho", "ux", "uy", "P"):
+        assert float((mo[k] - torch.tensor(mb[k])).abs().max()) < 1e-14, k
+
+
+@pytest.mark.parametrize("form", R.FORMS)
+@pytest.mark.parametrize("bc", BCS)
+def test_order_parameter_conserved(form, bc):
+    wx, wy, ulo, uhi, gx, gy = bc
+    p = R.Params(nx=24, ny=20, wall_x=wx, wall_y=wy, u_wall_lo=ulo, u_wall_hi=uhi, rho1=5.0, rho2=1.0,
+                 sigma=0.01, W=4.0, gx=gx, gy=gy)
+    phi0 = drop(24, 20, 6.0, 4.0, 11.3, 9.6)
+    st = R.init(p, phi0)
+    s0 = float(phi0.sum())
+    st = R.run(st, form, p, 30)
+    phi = R.moments(st, form, p)["phi"]
+    assert abs(float(phi.sum()) - s0) < 1e-11 * phi.numel()
+
+
+def test_rest_state_is_fixed_point():
+    """Uniform phi, u0 = 0, P0 = 0: f stays 0, u stays 0, h keeps its value."""
+    p = R.Params(nx=10, ny=6, rho1=4.0, rho2=1.0, sigma=0.02)
+    phi0 = torch.full((6, 10), 0.3)
+    st0 = R.init(p, phi0)
+    for form in R.FORMS:
+        st = R.run(dict(st0), form, p, 10)
+        assert float(st["f"].abs().max()) < 1e-18
+        assert float((st["h"] - st0["h"]).abs().max()) < 1e-15
+        m = R.moments(st, form, p)
+        assert float(m["ux"].abs().max()) < 1e-18 and float(m["uy"].abs().max()) < 1e-18
+
+
+@pytest.mark.parametrize("form", R.FORMS)
+def test_translation_equivariance(form):
+    """A periodic shift of the initial field shifts the solution, bit for bit."""
+    p = R.Params(nx=16, ny=12, rho1=10.0, rho2=1.0, sigma=0.01, W=3.0)
+    phi0 = drop(16, 12, 3.5, 3.0, 6.3, 5.1)
+    a = R.run(R.init(p, phi0), form, p, 5)
+    b = R.run(R.init(p, torch.roll(phi0, (3, 5), (0, 1))), form, p, 5)
+    for k in ("f", "h", "J"):
+        assert torch.equal(torch.roll(a[k], (3, 5), (1, 2)), b[k]), k
+
+
+@pytest.mark.parametrize("form", R.FORMS)
+def test_transpose_symmetry(form):
+    """Swapping x and y in the input swaps them (and the velocity components)
+    in the output: catches transposed operands in the force terms."""
+    p = R.Params(nx=14, ny=14, rho1=10.0, rho2=1.0, sigma=0.01, W=3.0)
+    phi0 = drop(14, 14, 3.5, 3.0, 6.3, 7.9)
+    a = R.moments(R.run(R.init(p, phi0), form, p, 6), form, p)
+    b = R.moments(R.run(R.init(p, phi0.T.contiguous()), form, p, 6), form, p)
+    assert float((a["phi"].T - b["phi"]).abs().max()) < 1e-14
+    assert float((a["ux"].T - b["uy"]).abs().max()) < 1e-16
+    assert float((a["uy"].T - b["ux"]).abs().max()) < 1e-16
+    assert float((a["P"].T - b["P"]).abs().max()) < 1e-16
+
+
+@pytest.mark.parametrize("form", R.FORMS)
+def test_centred_droplet_has_zero_net_momentum(form):
+    p = R.Params(nx=20, ny=20, rho1=10.0, rho2=1.0, sigma=0.01, W=3.0)
+    m = R.moments(R.run(R.init(p, drop(20, 20, 5.0, 3.0, 10.0, 10.0)), form, p, 20), form, p)
+    umax = float(torch.sqrt(m["ux"] ** 2 + m["uy"] ** 2).max())
+    assert umax > 0
+    assert abs(float((m["rho"] * m["ux"]).sum())) < 1e-12 * umax * 400
+    assert abs(float((m["rho"] * m["uy"]).sum())) < 1e-12 * umax * 400
+
+
+def test_couette_flow_exact():
+    """Half-way bounce-back with moving walls (Eq. 43): linear profile with the
+    wall speeds at y = -1/2 and y = ny - 1/2."""
+    p = R.Params(nx=4, ny=8, wall_y=1, u_wall_lo=-0.01, u_wall_hi=0.02, nu1=1 / 6, nu2=1 / 6, sigma=0.01)
+    st = R.run(R.init(p, torch.ones(8, 4)), "cpf2", p, 1200)
+    m = R.moments(st, "cpf2", p)
+    y = torch.arange(8.0)
+    exact = -0.01 + 0.03 * (y + 0.5) / 8
+    assert float((m["ux"] - exact.view(8, 1)).abs().max()) < 1e-10
+    assert float(m["uy"].abs().max()) < 1e-15
+
+
+def test_couette_flow_exact_on_x_walls():
+    p = R.Params(nx=8, ny=4, wall_x=1, u_wall_lo=0.015, u_wall_hi=-0.005, nu1=1 / 6, nu2=1 / 6, sigma=0.01)
+    st = R.run(R.init(p, torch.ones(4, 8)), "stf2", p, 1200)
+    m = R.moments(st, "stf2", p)
+    x = torch.arange(8.0)
+    exact = 0.015 - 0.02 * (x + 0.5) / 8
+    assert float((m["uy"] - exact.view(1, 8)).abs().max()) < 1e-10
+    assert float(m["ux"].abs().max()) < 1e-15
+
+
+def test_poiseuille_flow_exact():
+    """Body force F_g = (rho - rho0) g with rho0 = 0 between still walls: at
+    tau_f = 1/2 + sqrt(3)/4 half-way bounce-back with the forcing of Eq. (35)
+    and the velocity of Eq. (37) gives the exact parabola."""
+    tau = 0.5 + math.sqrt(3) / 4
+    nu, g, ny = (tau - 0.5) / 3, 1e-6, 12
+    p = R.Params(nx=4, ny=ny, wall_y=1, nu1=nu, nu2=nu, sigma=0.01, gx=g, rho0=0.0)
+    st = R.run(R.init(p, torch.ones(ny, 4)), "cpf2", p, 2500)
+    m = R.moments(st, "cpf2", p)
+    y = torch.arange(float(ny))
+    exact = g / (2 * nu) * (y + 0.5) * (ny - 0.5 - y)
+    assert float((m["ux"][:, 0] - exact).abs().max() / exact.max()) < 1e-7
+
+
+@pytest.mark.parametrize("form", R.FORMS)
+def test_flat_interface_is_stationary(form):
+    """tanh(2 r / W) (Eq. 4) with beta, kappa of Eq. (6) is the equilibrium of
+    a flat interface: at W = 8 the discrete profile moves by < 3e-3 in 400
+    steps (an interface width mis-set by sqrt(2) moves it by ~4e-2)."""
+    W, ny = 8.0, 96
+    yy = torch.arange(float(ny)).view(ny, 1).expand(ny, 4)
+    phi0 = torch.tanh(2 * (yy - 24) / W) - torch.tanh(2 * (yy - 72) / W) - 1
+    p = R.Params(nx=4, ny=ny, rho1=3.0, rho2=1.0, sigma=0.01, W=W, M=0.1)
+    m = R.moments(R.run(R.init(p, phi0), form, p, 400), form, p)
+    assert float((m["phi"] - phi0).abs().max()) < 3e-3
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("form", ["stf2", "cpf2", "pf2", "csf2"])
+def test_laplace_law(form):
+    """Stationary droplet (Sec. V.A): sigma_num = R_num (p_in - p_out) lies
+    within the error band the paper prints in Table I for W = 4 and R of
+    about 15 cells (largest error there: PF-2, 7.9%)."""
+    import json, os
+    tab = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table1_laplace.json")))
+    band = max(max(v) for v in tab["err_percent"].values()) / 100.0
+    n, r = 64, 16.0
+    p = R.Params(nx=n, ny=n, rho1=10.0, rho2=1.0, nu1=1 / 6, nu2=1 / 6, sigma=0.01, W=4.0, M=0.1)
+    st = R.run(R.init(p, drop(n, n, r, 4.0, n / 2, n / 2)), form, p, 3000)
+    sig, rn = R.laplace_sigma(R.moments(st, form, p), p)
+    assert abs(rn - r) < 0.5
+    assert abs(sig - p.sigma) / p.sigma < band, sig
+
