@@ -1,0 +1,181 @@
+"""Benchmark of the phase-field LBM hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+
+Workload: the stationary droplet on a 2048x2048 periodic lattice (R = 256,
+W = 5, density ratio 1000, dynamic viscosity ratio 100, sigma = 1e-3), one
+simulation per interfacial-force form; a "step" is one time step (fused
+collide-stream kernel + order-parameter kernel) of one of the eight
+simulations, taken round-robin, so K steps cover every form.  All state is
+resident in HBM before the timed region.
+
+Prints one JSON line with MLUPS, the roofline of the fused kernel (HIP
+events recorded on the launch stream during the timed region), the oracle
+timed on the host cores, per-form MLUPS and the batched/adjoint figures.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per node and launch (FP32 populations, FP64 phi):
+#   fused: read 9 f + P + 8 h (pulled) + 2 J + phi(8 B); write 9 f + P + 8 h + d0 + 2 J
+#   phi  : read d0 + 8 h (pulled) + phi(8 B); write phi(8 B)
+BYTES_FUSED = 9 * 4 + 4 + 8 * 4 + 2 * 4 + 8 + 9 * 4 + 4 + 9 * 4 + 2 * 4
+BYTES_PHI = 4 + 8 * 4 + 8 + 8
+FORMS = ("stf1", "stf2", "cpf1", "cpf2", "pf1", "pf2", "csf1", "csf2")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fused_droplet2048.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2012_14729_amd", "csrc", "lbm_kernels.hip")
+
+
+def kernel_sha():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per fused launch from the committed rocprofv3 counter runs,
+    or None when missing or taken on a different kernel source."""
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_sha") != kernel_sha():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(budget_s=20.0):
+    """The oracle (FP64, torch CPU) on the same 2048x2048 droplet: one warm-up
+    step, then steps until about budget_s seconds have passed."""
+    import numpy as np
+    import torch
+
+    import workloads as WL
+    from oracle import lbm_ref as R
+
+    p, phi0, _, _ = WL.config_droplet_large(2048)
+    op = R.Params(**{k: (None if k == "rho0" else v) for k, v in p.as_dict().items()})
+    st = R.init(op, torch.tensor(np.asarray(phi0, np.float32), dtype=torch.float64))
+    st = R.step(st, "stf1", op)
+    n, t0 = 0, time.perf_counter()
+    while True:
+        st = R.step(st, FORMS[n % 8], op)
+        n += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or n >= 64:
+            break
+    cells = p.nx * p.ny
+    return {"value": round(cells * n / el / 1e6, 3), "unit": "MLUPS", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{n} time steps of the 2048x2048 droplet (forms round-robin, FP64 torch CPU) after 1 warm-up step, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1600)
+    ap.add_argument("--warmup", type=int, default=80)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--size", type=int, default=2048)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (multi-GPU sharding is a "
+              f"design note, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2012_14729_amd as P
+    import workloads as WL
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    p, phi0, _, _ = WL.config_droplet_large(args.size)
+    phi0 = np.asarray(phi0, np.float32)
+    print(f"[bench] building {len(FORMS)} simulations {p.nx}x{p.ny}", file=sys.stderr, flush=True)
+    sims = [P.Simulation(p.as_dict(), phi0, device=dev) for _ in FORMS]
+    cells = p.nx * p.ny
+
+    for k in range(args.warmup):
+        sims[k % 8].step(1, FORMS[k % 8])
+    torch.cuda.synchronize()
+    print("[bench] warm-up done", file=sys.stderr, flush=True)
+
+    for s in sims:
+        s.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        sims[k % 8].step(1, FORMS[k % 8])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    fused_ms = sum(s.kernel_time(0)[0] for s in sims)
+    fused_n = sum(s.kernel_time(0)[1] for s in sims)
+    phi_ms = sum(s.kernel_time(1)[0] for s in sims)
+    phi_n = sum(s.kernel_time(1)[1] for s in sims)
+    for s in sims:
+        s.set_timing(False)
+    print(f"[bench] timed {args.steps} steps in {el:.3f} s", file=sys.stderr, flush=True)
+
+    diverged = [f for f, s in zip(FORMS, sims) if s.status()]
+    umax = {}
+    for f, s in zip(FORMS, sims):
+        m = s.moments(f)
+        umax[f] = float(torch.sqrt(m["ux"] ** 2 + m["uy"] ** 2).max())
+
+    # per-form rates, each form alone
+    per_form = {}
+    nper = max(8, args.steps // 16)
+    for f, s in zip(FORMS, sims):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s.step(nper, f)
+        torch.cuda.synchronize()
+        per_form[f] = round(cells * nper / (time.perf_counter() - t1) / 1e6, 1)
+
+    fused_avg_s = fused_ms / max(fused_n, 1) / 1e3
+    achieved = BYTES_FUSED * cells / fused_avg_s / 1e9
+    traffic = measured_traffic()
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_fused (collide-stream, all forms)", "bytes_per_node": BYTES_FUSED,
+                "avg_launch_us": round(fused_avg_s * 1e6, 2),
+                "phi_kernel": {"avg_launch_us": round(phi_ms / max(phi_n, 1) * 1e3, 2),
+                               "achieved_GBs": round(BYTES_PHI * cells / (phi_ms / max(phi_n, 1) / 1e3) / 1e9, 1)}}
+
+    value = cells * args.steps / el / 1e6
+    out = {
+        "metric": "MLUPS & HBM GB/s (% peak) FP32 1 GPU; batched/adjoint vs plain step",
+        "value": round(value, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(el / args.steps * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"stationary droplet {p.nx}x{p.ny} periodic, R={p.nx // 8}, W=5, rho1/rho2=1000, "
+                               f"mu1/mu2=100, sigma=1e-3, 8 force forms round-robin",
+                   "precision": "FP32 populations and collision; FP64 order parameter and stencil/force stage",
+                   "step_bytes_per_node": BYTES_FUSED + BYTES_PHI,
+                   "step_GBs": round((BYTES_FUSED + BYTES_PHI) * value * 1e6 / 1e9, 1)},
+        "roofline": roofline,
+        "per_form_MLUPS": per_form,
+        "spurious_umax": {k: float(f"{v:.4g}") for k, v in umax.items()},
+        "diverged": diverged,
+        "batched": None,
+        "adjoint": None,
+    }
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,164 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) phase-field lattice Boltzmann library.
+ *
+ * The library advances the coupled D2Q9 lattice Boltzmann equations of
+ * Zhang, Liang & Guo, "On the formulations of interfacial force in the
+ * phase-field-based lattice Boltzmann method" (arXiv:2012.14729):
+ *   flow populations f_i   (Sec. III, Eq. 29, equilibrium Eq. 31, forcing Eq. 35)
+ *   order-parameter h_i    (Sec. III, Eq. 30, equilibrium Eq. 32, forcing Eq. 36)
+ * with the chemical potential of Sec. II.A (Eq. 2), one of the eight
+ * interfacial forces of Sec. II.B, the macroscopic moments of Eq. (37), the
+ * isotropic difference stencils of Eqs. (41)-(42) and half-way bounce-back
+ * walls (Sec. IV, Eqs. 43-44).  Lattice units: dx = dt = 1, cs^2 = 1/3.
+ *
+ * Conventions shared by every entry point
+ *  - Return value: LBM_OK (0) on success, a negative lbm_status_code on
+ *    failure; nothing throws across the ABI.  lbm_last_error() returns a
+ *    thread-local message for the last failing call.
+ *  - Device pointers ("d_" prefix) are HIP device addresses on the current
+ *    device; host pointers ("h_" prefix or plain scalars) are ordinary memory.
+ *  - Every call that takes a `stream` (a hipStream_t passed as void*, NULL
+ *    for the null stream) is asynchronous on that stream unless it says it
+ *    synchronises.  Arguments are validated on the host before any launch.
+ *  - Fields are FP32, row-major [ny][nx] with x fastest and no padding
+ *    (element (x, y) at offset y*nx + x).  Node (x, y) sits at lattice
+ *    position (x, y); half-way walls lie at x = -1/2, nx - 1/2 (wall_x) or
+ *    y = -1/2, ny - 1/2 (wall_y).
+ *  - Ownership: the caller allocates and owns all device memory (workspace,
+ *    inputs, outputs).  The library owns only the small host handles, which
+ *    the matching *_destroy call frees.  No entry point allocates device
+ *    memory except lbm_batch_create, which allocates nothing either: the
+ *    caller passes the batch workspace.
+ */
+#ifndef PFLBM_LBM_H
+#define PFLBM_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Interfacial force F_sf, in the paper's order (Sec. II.B). */
+enum lbm_force_form {
+  LBM_STF1 = 0, /* -div(kappa grad(phi) (x) grad(phi))                         Eq. (17) */
+  LBM_STF2 = 1, /*  div(kappa (|grad phi|^2 I - grad(phi) (x) grad(phi)))      Eq. (18) */
+  LBM_CPF1 = 2, /* -phi grad(mu_phi)                                           Eq. (20) */
+  LBM_CPF2 = 3, /*  mu_phi grad(phi)                                           Eq. (20) */
+  LBM_PF1 = 4,  /* -kappa grad(phi) lap(phi)                                   Eq. (20) */
+  LBM_PF2 = 5,  /*  kappa phi grad(lap phi)                                    Eq. (20) */
+  LBM_CSF1 = 6, /* -kappa |grad phi|^2 n div(n), n = grad phi/sqrt(|grad phi|^2+eps^2)  Eq. (24) */
+  LBM_CSF2 = 7, /* -(sigma/2) grad(phi) div(n)                                 Eq. (25) */
+  LBM_NUM_FORMS = 8
+};
+
+enum lbm_status_code {
+  LBM_OK = 0,
+  LBM_E_INVAL = -1,       /* bad argument; nothing was launched                        */
+  LBM_E_HIP = -2,         /* a HIP runtime call failed; message in lbm_last_error()    */
+  LBM_E_DIVERGED = -3,    /* a non-finite velocity or order parameter was produced    */
+  LBM_E_UNSUPPORTED = -4  /* valid request the library does not implement             */
+};
+
+/* Problem statement in lattice units (Sec. II.A, Sec. III, Sec. IV).
+ * Validation (LBM_E_INVAL): nx, ny >= 8; wall_x, wall_y in {0, 1}; at most
+ * one walled axis may have moving walls; rho1, rho2 > 0; nu1, nu2 > 0 (so
+ * tau_f = 1/2 + 3 nu > 1/2 everywhere); sigma >= 0; W > 0; M >= 0;
+ * tau_h > 1/2; eps_n > 0; all finite except rho0, which may be NaN. */
+typedef struct lbm_params {
+  int32_t nx, ny;          /* nodes along x and y                                          */
+  int32_t wall_x, wall_y;  /* 0: periodic axis; 1: half-way bounce-back walls on that axis   */
+  double u_wall_lo;        /* tangential speed of the low wall of the walled axis (Eq. 43):  */
+  double u_wall_hi;        /*   a y-wall moves along +x, an x-wall along +y                   */
+  double rho1, rho2;       /* densities of fluid 1 (phi = +1) and fluid 2 (phi = -1) (Eq. 9) */
+  double nu1, nu2;         /* kinematic viscosities; mu = rho nu is linear in phi (Eq. 10)   */
+  double sigma, W;         /* surface tension, interface width: beta = 3 sigma/(4 W),        */
+                           /*   kappa = 3 W sigma / 8 (Eq. 6)                                */
+  double M, tau_h;         /* mobility and CH relaxation time: M = cs^2 eta (tau_h - 1/2)    */
+  double gx, gy;           /* gravity; F_g = (rho - rho0) g (Eq. 8)                          */
+  double rho0;             /* background density; NaN: mean of rho(phi0) over the domain    */
+  double eps_n;            /* regulariser of the CSF interface normal (1e-6 is typical)      */
+} lbm_params;
+
+typedef struct lbm_sim lbm_sim;
+typedef struct lbm_batch lbm_batch;
+
+/* Bytes of device workspace one simulation needs (state of two population
+ * sets, the order parameter in FP64, the (phi u) history and small scratch). */
+int lbm_workspace_bytes(const lbm_params* p, size_t* bytes);
+
+/* Create a simulation on the caller's workspace (>= lbm_workspace_bytes,
+ * 256-byte aligned) and initialise it from phi0 (and u0; d_ux0 and d_uy0 may
+ * both be NULL for u0 = 0): P0 = 0, f = f^eq(P0, rho(phi0), u0),
+ * h = h^eq(phi0, mu_phi(phi0), u0), (phi u)^(-1) = phi0 u0 (Eqs. 31-32).
+ * If p->rho0 is NaN the call synchronises `stream` once to fix rho0.
+ * The workspace must stay allocated until lbm_destroy.  The inputs may be
+ * freed when the call returns (they are consumed on `stream`). */
+int lbm_init(lbm_sim** sim, const lbm_params* p, void* d_ws, size_t ws_bytes,
+             const float* d_phi0, const float* d_ux0, const float* d_uy0, void* stream);
+
+/* Advance nsteps >= 0 time steps (Eqs. 29-30: collide with the given force
+ * form, stream with bounce-back).  Asynchronous; no host synchronisation. */
+int lbm_step(lbm_sim* sim, int32_t nsteps, int32_t force_form, void* stream);
+
+/* Macroscopic fields of the current state (Eq. 37): phi = sum h_i, rho(phi)
+ * (Eq. 9), u = [sum c_i f_i + (cs^2/2)(F_sf + F_g)] / (cs^2 rho) and
+ * P_sf = sum f_i + (cs^2/2) u.grad(rho).  u depends on the force form, so it
+ * is an argument.  Any output pointer may be NULL to skip that field.  Each
+ * output holds nx*ny floats. */
+int lbm_moments(lbm_sim* sim, int32_t force_form, float* d_phi, float* d_rho, float* d_ux, float* d_uy,
+                float* d_p, void* stream);
+
+/* Host-side query: synchronises `stream`; *diverged = 1 if any step since
+ * init produced a non-finite velocity or order parameter, else 0.  Returns
+ * LBM_E_DIVERGED in that case (with *diverged = 1). */
+int lbm_status(lbm_sim* sim, int32_t* diverged, void* stream);
+
+/* Number of completed time steps since init (host counter). */
+int lbm_get_step(const lbm_sim* sim, int64_t* step);
+
+/* Checkpoint: the complete state (populations, FP64 order parameter, (phi u)
+ * history, step counter) copied to/from a caller-owned device blob of
+ * lbm_state_bytes bytes.  Restoring and stepping reproduces an uninterrupted
+ * run bit for bit. */
+int lbm_state_bytes(const lbm_sim* sim, size_t* bytes);
+int lbm_save(lbm_sim* sim, void* d_blob, void* stream);
+int lbm_restore(lbm_sim* sim, const void* d_blob, void* stream);
+
+/* Kernel timing with HIP events recorded on the launch stream around every
+ * launch of one kernel.  kernel: 0 = fused collide-stream kernel, 1 = order
+ * parameter kernel.  lbm_kernel_time synchronises and returns the summed
+ * elapsed milliseconds and the number of timed launches since the last reset;
+ * enabling resets the counters. */
+int lbm_set_timing(lbm_sim* sim, int32_t enable);
+int lbm_kernel_time(lbm_sim* sim, int32_t kernel, double* total_ms, int64_t* launches);
+
+int lbm_destroy(lbm_sim* sim);
+
+/* ------------------------------------------------------------------------
+ * Batched: `count` independent simulations of uneven size and force form
+ * advanced together by persistent kernels replayed from a captured HIP graph.
+ * params[k] and forms[k] describe instance k (periodic axes only in this
+ * version: wall_x = wall_y = 0, else LBM_E_UNSUPPORTED); d_phi0 is a host
+ * array of `count` device pointers to each instance's nx*ny initial field.
+ * ------------------------------------------------------------------------ */
+int lbm_batch_workspace_bytes(const lbm_params* params, int32_t count, size_t* bytes);
+int lbm_batch_create(lbm_batch** batch, const lbm_params* params, const int32_t* forms, int32_t count,
+                     void* d_ws, size_t ws_bytes, const float* const* d_phi0, void* stream);
+/* Advance every instance by nsteps (asynchronous). */
+int lbm_batch_step(lbm_batch* batch, int32_t nsteps, void* stream);
+/* Moments of instance k, same definitions and layout as lbm_moments. */
+int lbm_batch_moments(lbm_batch* batch, int32_t k, float* d_phi, float* d_rho, float* d_ux, float* d_uy,
+                      float* d_p, void* stream);
+/* Synchronises; h_flags[k] = 1 if instance k diverged, else 0. */
+int lbm_batch_status(lbm_batch* batch, int32_t* h_flags, void* stream);
+int lbm_batch_destroy(lbm_batch* batch);
+
+const char* lbm_last_error(void);
+const char* lbm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PFLBM_LBM_H */

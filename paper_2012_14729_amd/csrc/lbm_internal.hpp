@@ -1,0 +1,87 @@
+// Internal declarations shared by the HIP kernels and the C-ABI host code.
+//
+// D2Q9 lattice of arXiv:2012.14729, Sec. III (Eq. 34 and the weights below
+// it), stored as constexpr functions so fully unrolled loops fold them into
+// immediates.  Device state layout (structure of arrays, x fastest):
+//   f[2][9] planes  FP32  post-collision flow populations minus w_i P of the
+//                         storing node (ping-pong)
+//   P[2]    planes  FP32  pressure P_sf of the storing node (ping-pong)
+//   h[2][9] planes  FP32  post-collision order-parameter populations; slot 0
+//                         holds d0 = h_0^+ - phi (a small deviation) instead of h_0^+
+//   J[2]    planes  FP32  (phi u) of the previous step, updated in place
+//   phi     plane   FP64  order parameter, updated in place
+// A plane is `pitch * ny` elements; element (x, y) is at y * pitch + x.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pflbm {
+
+__host__ __device__ constexpr int cx(int i) { return (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0); }
+__host__ __device__ constexpr int cy(int i) { return (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0); }
+__host__ __device__ constexpr float wt(int i) { return i == 0 ? 4.0f / 9.0f : (i < 5 ? 1.0f / 9.0f : 1.0f / 36.0f); }
+__host__ __device__ constexpr double wtd(int i) { return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0); }
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : (i < 5 ? ((i + 1) % 4) + 1 : ((i - 3) % 4) + 5); }
+
+constexpr int kTX = 64;   // tile width  (one wavefront row)
+constexpr int kTY = 8;    // tile height
+constexpr int kThreads = 256;
+
+// Per-simulation physical constants in the form the kernels use.
+struct Phys {
+  float rho_a, rho_b;     // rho(phi) = rho_a + rho_b phi      (Eq. 9)
+  float mu_a, mu_b;       // mu(phi)  = mu_a + mu_b phi        (Eq. 10)
+  float beta4, kappa;     // 4 beta, kappa                      (Eq. 6)
+  float sigma_half;       // sigma / 2 (CSF-2)
+  float eps2;             // eps_n^2 (CSF normal regulariser)
+  float eta;              // M / (cs^2 (tau_h - 1/2))
+  float a_h;              // 3 tau_2 / (tau_h tau_1)            (Eq. 36)
+  float inv_tau_h;        // 1 / tau_h
+  float gx, gy, rho0;     // F_g = (rho - rho0) g
+  float uw_lo, uw_hi;     // wall speeds
+  int wall_x, wall_y;
+  double beta4_d, kappa_d, sigma_half_d, eps2_d;   // FP64 copies for the stencil stages
+  double rho2_d, drho_half_d, mu2_d, dmu_half_d;   // rho = rho2 + (rho1-rho2)(1+phi)/2, same for mu
+  double eta_d, a_h_d, inv_tau_h_d, gx_d, gy_d, rho0_d, uw_lo_d, uw_hi_d;
+};
+
+struct Grid {
+  int nx, ny, pitch;
+  long long ps;           // plane stride in elements
+};
+
+struct StepArgs {
+  const float* fin;
+  float* fout;
+  const float* pin;
+  float* pout;
+  const float* hin;
+  float* hout;
+  float* J;
+  const double* phi;
+  int* status;
+  Grid g;
+  Phys c;
+};
+
+struct MomentArgs {
+  float* phi;
+  float* rho;
+  float* ux;
+  float* uy;
+  float* p;
+};
+
+// kernel launchers (lbm_kernels.hip); each returns the launch error code
+hipError_t launch_fused(int form, const StepArgs& a, hipStream_t s);
+hipError_t launch_moments(int form, const StepArgs& a, const MomentArgs& m, hipStream_t s);
+hipError_t launch_phi(const float* h, double* phi, const Grid& g, int wall_x, int wall_y, hipStream_t s);
+hipError_t launch_init(const float* phi0, const float* ux0, const float* uy0, float* f_tmp, float* h_tmp,
+                       float* f_out, float* h_out, float* J, double* phi, float* P, const Grid& g, const Phys& c,
+                       hipStream_t s);
+hipError_t launch_phi_sum(const double* phi, const Grid& g, double* partial, int npartial, double* out,
+                          hipStream_t s);
+hipError_t launch_fill_int(int* p, int value, int n, hipStream_t s);
+
+}  // namespace pflbm

@@ -1,0 +1,654 @@
+// HIP kernels (gfx950, wave64) of the phase-field lattice Boltzmann step of
+// arXiv:2012.14729.
+//
+// One time step is two launches:
+//   k_fused<FORM>  pull-stream f and h (with bounce-back), compute phi
+//                  stencils, mu_phi, the interfacial force, u, P, div(phi u),
+//                  d_t(phi u), collide both populations and store them
+//                  (structure of arrays, coalesced rows).
+//   k_phi          phi^{n+1} = phi^n + d0 + sum_{i>=1} h_i pulled, in FP64.
+//
+// The fused kernel works on 64x8 tiles.  The order parameter is staged in LDS
+// with a 3-node halo (FP64); second-level stencil fields live on the 2-node
+// ring, the velocity on the 1-node ring.  Only nearest-neighbour pulls touch
+// HBM; everything with a wider footprint comes from LDS.
+#include "lbm_internal.hpp"
+
+namespace pflbm {
+
+namespace {
+
+constexpr int PW = kTX + 6, PH = kTY + 6;   // phi tile (halo 3)
+constexpr int BW = kTX + 4, BH = kTY + 4;   // second-level fields (halo 2)
+constexpr int UW = kTX + 2, UH = kTY + 2;   // velocity ring (halo 1)
+constexpr int NRING = 2 * UW + 2 * kTY;     // positions of the velocity ring
+constexpr float CS2 = 1.0f / 3.0f;
+
+__device__ __forceinline__ int wrap_or_reflect(int c, int n, int wall) {
+  if (wall) {
+    if (c < 0) c = -1 - c;
+    else if (c >= n) c = 2 * n - 1 - c;
+    return c < 0 ? 0 : (c >= n ? n - 1 : c);   // positions no active node reads
+  }
+  c %= n;
+  return c < 0 ? c + n : c;
+}
+
+// Pull population i for node (x, y) (x, y inside the domain): the value that
+// left x - c_i in direction i; if x - c_i lies beyond a wall the slot opp(i)
+// of x itself holds the bounced population (wall term applied at store time).
+template <int I>
+__device__ __forceinline__ float pull(const float* __restrict__ base, int x, int y, const Grid& g, int wx, int wy) {
+  int sx = x - cx(I), sy = y - cy(I);
+  bool bounce = false;
+  if (cx(I) != 0) {
+    if (wx) bounce |= (sx < 0) | (sx >= g.nx);
+    else sx = sx < 0 ? sx + g.nx : (sx >= g.nx ? sx - g.nx : sx);
+  }
+  if (cy(I) != 0) {
+    if (wy) bounce |= (sy < 0) | (sy >= g.ny);
+    else sy = sy < 0 ? sy + g.ny : (sy >= g.ny ? sy - g.ny : sy);
+  }
+  if (bounce) return base[(long long)opp(I) * g.ps + (long long)y * g.pitch + x];
+  return base[(long long)I * g.ps + (long long)sy * g.pitch + sx];
+}
+
+// Source of the pulled population i for node (x, y): the offset of the node
+// it is read from and the slot, following the same rule as pull<I>.
+template <int I>
+__device__ __forceinline__ long long src_off(int x, int y, const Grid& g, int wx, int wy, int& slot) {
+  int sx = x - cx(I), sy = y - cy(I);
+  bool bounce = false;
+  if (cx(I) != 0) {
+    if (wx) bounce |= (sx < 0) | (sx >= g.nx);
+    else sx = sx < 0 ? sx + g.nx : (sx >= g.nx ? sx - g.nx : sx);
+  }
+  if (cy(I) != 0) {
+    if (wy) bounce |= (sy < 0) | (sy >= g.ny);
+    else sy = sy < 0 ? sy + g.ny : (sy >= g.ny ? sy - g.ny : sy);
+  }
+  slot = bounce ? opp(I) : I;
+  return bounce ? (long long)y * g.pitch + x : (long long)sy * g.pitch + sx;
+}
+
+// Mixture density and viscosity (Eqs. 9-10) from the FP64 order parameter,
+// written as rho2 + (rho1 - rho2)(1 + phi)/2 so a light phase keeps its
+// relative precision.
+__device__ __forceinline__ double rho_of(double phi, const Phys& c) { return c.rho2_d + c.drho_half_d * (1.0 + phi); }
+__device__ __forceinline__ double mu_of(double phi, const Phys& c) { return c.mu2_d + c.dmu_half_d * (1.0 + phi); }
+
+struct Lds {
+  double phi[PH][PW];
+  double b[3][BH][BW];
+  float u[2][UH][UW];
+};
+
+// gradient and Laplacian of phi at sPhi position (py, px) (Eqs. 41-42), in
+// FP64 from differences to the centre value.
+__device__ __forceinline__ void grad_lap_phi(const Lds& s, int py, int px, double& gx, double& gy, double& lap) {
+  const double c = s.phi[py][px];
+  double sx = 0.0, sy = 0.0, sl = 0.0;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const double d = s.phi[py + cy(i)][px + cx(i)] - c;
+    if (cx(i) != 0) sx += (wtd(i) * cx(i)) * d;
+    if (cy(i) != 0) sy += (wtd(i) * cy(i)) * d;
+    sl += wtd(i) * d;
+  }
+  gx = 3.0 * sx;
+  gy = 3.0 * sy;
+  lap = 6.0 * sl;
+}
+
+// mu_phi = 4 beta phi (phi^2 - 1) - kappa lap(phi)   (Eq. 2)
+__device__ __forceinline__ double chem_pot(double phi, double lap, const Phys& c) {
+  return c.beta4_d * phi * ((phi - 1.0) * (phi + 1.0)) - c.kappa_d * lap;
+}
+
+// isotropic gradient of an LDS field at (by, bx)  (Eq. 41)
+__device__ __forceinline__ void grad_b(const double (*f)[BW], int by, int bx, double& gx, double& gy) {
+  const double c = f[by][bx];
+  double sx = 0.0, sy = 0.0;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const double d = f[by + cy(i)][bx + cx(i)] - c;
+    if (cx(i) != 0) sx += (wtd(i) * cx(i)) * d;
+    if (cy(i) != 0) sy += (wtd(i) * cy(i)) * d;
+  }
+  gx = 3.0 * sx;
+  gy = 3.0 * sy;
+}
+
+// Stage B: form-specific node field(s) on the 2-ring (FP64: their stencil
+// differences are small against their values).
+template <int FORM>
+__device__ __forceinline__ void stage_b(Lds& s, int tid, const Phys& c) {
+  if constexpr (FORM == 3 || FORM == 4) return;   // CPF-2, PF-1: pointwise at radius 1
+  const double kappa = c.kappa_d;
+  for (int k = tid; k < BH * BW; k += kThreads) {
+    const int by = k / BW, bx = k - by * BW;
+    const int py = by + 1, px = bx + 1;
+    double gx, gy, lap;
+    grad_lap_phi(s, py, px, gx, gy, lap);
+    if constexpr (FORM == 0) {          // STF-1: T = -kappa G (x) G, F = div T
+      s.b[0][by][bx] = -kappa * gx * gx;
+      s.b[1][by][bx] = -kappa * gx * gy;
+      s.b[2][by][bx] = -kappa * gy * gy;
+    } else if constexpr (FORM == 1) {   // STF-2: T = kappa (|G|^2 I - G (x) G)
+      s.b[0][by][bx] = kappa * gy * gy;
+      s.b[1][by][bx] = -kappa * gx * gy;
+      s.b[2][by][bx] = kappa * gx * gx;
+    } else if constexpr (FORM == 2) {   // CPF-1: mu_phi
+      s.b[0][by][bx] = chem_pot(s.phi[py][px], lap, c);
+    } else if constexpr (FORM == 5) {   // PF-2: lap(phi)
+      s.b[0][by][bx] = lap;
+    } else {                            // CSF-1/2: n = G / sqrt(|G|^2 + eps^2)
+      const double inv = 1.0 / sqrt(gx * gx + gy * gy + c.eps2_d);
+      s.b[0][by][bx] = gx * inv;
+      s.b[1][by][bx] = gy * inv;
+    }
+  }
+}
+
+// Interfacial force at velocity-ring position (uy_, ux_) (Sec. II.B), in FP64.
+// sPhi index of that node is (uy_ + 2, ux_ + 2); stage-B index (uy_ + 1, ux_ + 1).
+template <int FORM>
+__device__ __forceinline__ void force_sf(const Lds& s, int uy_, int ux_, const Phys& c, double& fxo, double& fyo) {
+  const int py = uy_ + 2, px = ux_ + 2, by = uy_ + 1, bx = ux_ + 1;
+  const double kappa = c.kappa_d;
+  double fx, fy;
+  if constexpr (FORM == 0 || FORM == 1) {   // div T
+    double sx = 0.0, sy = 0.0;
+    const double txx = s.b[0][by][bx], txy = s.b[1][by][bx], tyy = s.b[2][by][bx];
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      const int ny_ = by + cy(i), nx_ = bx + cx(i);
+      const double dxx = s.b[0][ny_][nx_] - txx, dxy = s.b[1][ny_][nx_] - txy, dyy = s.b[2][ny_][nx_] - tyy;
+      sx += wtd(i) * ((double)cx(i) * dxx + (double)cy(i) * dxy);
+      sy += wtd(i) * ((double)cx(i) * dxy + (double)cy(i) * dyy);
+    }
+    fx = 3.0 * sx;
+    fy = 3.0 * sy;
+  } else if constexpr (FORM == 2) {         // CPF-1: -phi grad(mu)
+    double gx, gy;
+    grad_b(s.b[0], by, bx, gx, gy);
+    const double phi = s.phi[py][px];
+    fx = -phi * gx;
+    fy = -phi * gy;
+  } else if constexpr (FORM == 3) {         // CPF-2: mu grad(phi)
+    double gx, gy, lap;
+    grad_lap_phi(s, py, px, gx, gy, lap);
+    const double mu = chem_pot(s.phi[py][px], lap, c);
+    fx = mu * gx;
+    fy = mu * gy;
+  } else if constexpr (FORM == 4) {         // PF-1: -kappa grad(phi) lap(phi)
+    double gx, gy, lap;
+    grad_lap_phi(s, py, px, gx, gy, lap);
+    fx = -kappa * gx * lap;
+    fy = -kappa * gy * lap;
+  } else if constexpr (FORM == 5) {         // PF-2: kappa phi grad(lap phi)
+    double gx, gy;
+    grad_b(s.b[0], by, bx, gx, gy);
+    const double k = kappa * s.phi[py][px];
+    fx = k * gx;
+    fy = k * gy;
+  } else {                                  // CSF: div n
+    double dn = 0.0;
+    const double nxc = s.b[0][by][bx], nyc = s.b[1][by][bx];
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      const double dx = s.b[0][by + cy(i)][bx + cx(i)] - nxc;
+      const double dy = s.b[1][by + cy(i)][bx + cx(i)] - nyc;
+      dn += wtd(i) * ((double)cx(i) * dx + (double)cy(i) * dy);
+    }
+    dn *= 3.0;
+    double gx, gy, lap;
+    grad_lap_phi(s, py, px, gx, gy, lap);
+    if constexpr (FORM == 6) {              // CSF-1: -kappa |G|^2 n div n
+      const double k = -kappa * (gx * gx + gy * gy) * dn;
+      fx = k * nxc;
+      fy = k * nyc;
+    } else {                                // CSF-2: -(sigma/2) G div n
+      fx = -c.sigma_half_d * gx * dn;
+      fy = -c.sigma_half_d * gy * dn;
+    }
+  }
+  fxo = fx;
+  fyo = fy;
+}
+
+// Everything the collision of an active node needs (FP64 arithmetic, FP32
+// storage).  The flow populations are kept relative to the node's new
+// pressure: f[i] = f_i - w_i Pn.
+struct NodeState {
+  float f[9];
+  float Pn;
+  double ux, uy, fx, fy, rho, P, grx, gry, mu;
+};
+
+#define PULL_FP(I)                                                \
+  {                                                               \
+    int sl_;                                                      \
+    const long long o_ = src_off<I>(x, y, a.g, wx, wy, sl_);      \
+    ft[I] = a.fin[(long long)sl_ * a.g.ps + o_];                  \
+    ps[I] = a.pin[o_];                                            \
+  }
+
+// Velocity (and, for active nodes, the rest of Eq. 37) at a node whose
+// velocity-ring position is (uy_, ux_) and global position (x, y) inside the
+// domain.  The stored flow populations are deviations from the pressure of
+// the node that stored them: f_i = ft_i + w_i ps_i.
+template <int FORM, bool FULL>
+__device__ __forceinline__ void velocity_at(const Lds& s, const StepArgs& a, int uy_, int ux_, int x, int y,
+                                            NodeState& ns) {
+  double fx, fy;
+  force_sf<FORM>(s, uy_, ux_, a.c, fx, fy);
+  const double phid = s.phi[uy_ + 2][ux_ + 2];
+  const double rho = rho_of(phid, a.c);
+  fx += (rho - a.c.rho0_d) * a.c.gx_d;   // F_g = (rho - rho0) g   (Eq. 8)
+  fy += (rho - a.c.rho0_d) * a.c.gy_d;
+  const int wx = a.c.wall_x, wy = a.c.wall_y;
+  float ft[9], ps[9];
+  PULL_FP(0) PULL_FP(1) PULL_FP(2) PULL_FP(3) PULL_FP(4) PULL_FP(5) PULL_FP(6) PULL_FP(7) PULL_FP(8)
+  double jx = 0.0, jy = 0.0;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const double fi = (double)ft[i] + wtd(i) * (double)ps[i];
+    if (cx(i) != 0) jx += cx(i) * fi;
+    if (cy(i) != 0) jy += cy(i) * fi;
+  }
+  const double inv_rho = 1.0 / rho;
+  const double ux = (3.0 * jx + 0.5 * fx) * inv_rho;   // Eq. (37)
+  const double uy = (3.0 * jy + 0.5 * fy) * inv_rho;
+  ns.ux = ux;
+  ns.uy = uy;
+  if constexpr (FULL) {
+    double gx, gy, lap;
+    grad_lap_phi(s, uy_ + 2, ux_ + 2, gx, gy, lap);
+    ns.fx = fx;
+    ns.fy = fy;
+    ns.rho = rho;
+    ns.grx = a.c.drho_half_d * gx;   // grad rho = (rho1 - rho2)/2 grad phi
+    ns.gry = a.c.drho_half_d * gy;
+    ns.mu = chem_pot(phid, lap, a.c);
+    double sumf = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) sumf += (double)ft[i] + wtd(i) * (double)ps[i];
+    const double P = sumf + (ux * ns.grx + uy * ns.gry) * (0.5 / 3.0);   // Eq. (37)
+    const float Pn = (float)P;
+    ns.P = P;
+    ns.Pn = Pn;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) ns.f[i] = (float)((double)ft[i] + wtd(i) * ((double)ps[i] - (double)Pn));
+  }
+}
+
+__device__ __forceinline__ bool in_domain(int x, int y, const Grid& g) { return x >= 0 && x < g.nx && y >= 0 && y < g.ny; }
+
+// Velocity-ring position k -> (uy_, ux_)
+__device__ __forceinline__ void ring_pos(int k, int& uy_, int& ux_) {
+  if (k < UW) { uy_ = 0; ux_ = k; }
+  else if (k < 2 * UW) { uy_ = UH - 1; ux_ = k - UW; }
+  else if (k < 2 * UW + kTY) { uy_ = k - 2 * UW + 1; ux_ = 0; }
+  else { uy_ = k - 2 * UW - kTY + 1; ux_ = UW - 1; }
+}
+
+// Global position of ring position, wrapped on periodic axes; returns false
+// when it lies beyond a wall (its velocity is then never read directly).
+__device__ __forceinline__ bool ring_global(int uy_, int ux_, int x0, int y0, const StepArgs& a, int& x, int& y) {
+  x = x0 + ux_ - 1;
+  y = y0 + uy_ - 1;
+  if (a.c.wall_x) { if (x < 0 || x >= a.g.nx) return false; }
+  else { x %= a.g.nx; if (x < 0) x += a.g.nx; }
+  if (a.c.wall_y) { if (y < 0 || y >= a.g.ny) return false; }
+  else { y %= a.g.ny; if (y < 0) y += a.g.ny; }
+  return true;
+}
+
+template <int FORM, bool MOMENTS>
+__global__ __launch_bounds__(kThreads) void k_fused(StepArgs a, MomentArgs m) {
+  __shared__ Lds s;
+  const int tid = threadIdx.x;
+  const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY;
+  const int lx = tid & (kTX - 1), ty = tid >> 6;   // column, first row (rows ty, ty + 4)
+  const Grid& g = a.g;
+
+  // Stage A: phi tile with a 3-node halo (periodic wrap / even reflection at walls, Sec. IV)
+  for (int k = tid; k < PH * PW; k += kThreads) {
+    const int py = k / PW, px = k - py * PW;
+    const int gx = wrap_or_reflect(x0 + px - 3, g.nx, a.c.wall_x);
+    const int gy = wrap_or_reflect(y0 + py - 3, g.ny, a.c.wall_y);
+    s.phi[py][px] = a.phi[(long long)gy * g.pitch + gx];
+  }
+  __syncthreads();
+
+  stage_b<FORM>(s, tid, a.c);
+  __syncthreads();
+
+  // Stage C: velocity (and moments) on the tile and, for the step, its ring.
+  NodeState ns[2];
+  bool act[2];
+  int gxs[2], gys[2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int uy_ = ty + 4 * r + 1, ux_ = lx + 1;
+    int x, y;
+    const bool valid = ring_global(uy_, ux_, x0, y0, a, x, y);
+    act[r] = (x0 + lx < g.nx) && (y0 + ty + 4 * r < g.ny);
+    gxs[r] = x;
+    gys[r] = y;
+    if (valid) {
+      velocity_at<FORM, true>(s, a, uy_, ux_, x, y, ns[r]);
+      if constexpr (!MOMENTS) {
+        s.u[0][uy_][ux_] = (float)ns[r].ux;
+        s.u[1][uy_][ux_] = (float)ns[r].uy;
+      }
+    }
+  }
+  if constexpr (MOMENTS) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      if (!act[r]) continue;
+      const long long o = (long long)gys[r] * g.nx + gxs[r];
+      if (m.phi) m.phi[o] = (float)s.phi[ty + 4 * r + 3][lx + 3];
+      if (m.rho) m.rho[o] = (float)ns[r].rho;
+      if (m.ux) m.ux[o] = (float)ns[r].ux;
+      if (m.uy) m.uy[o] = (float)ns[r].uy;
+      if (m.p) m.p[o] = (float)ns[r].P;
+    }
+    return;
+  } else {
+    if (tid < NRING) {
+      int uy_, ux_, x, y;
+      ring_pos(tid, uy_, ux_);
+      if (ring_global(uy_, ux_, x0, y0, a, x, y)) {
+        NodeState rs;
+        velocity_at<FORM, false>(s, a, uy_, ux_, x, y, rs);
+        s.u[0][uy_][ux_] = (float)rs.ux;
+        s.u[1][uy_][ux_] = (float)rs.uy;
+      }
+    }
+    __syncthreads();
+
+    const Phys& c = a.c;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      if (!act[r]) continue;
+      const int x = gxs[r], y = gys[r];
+      const int uy_ = ty + 4 * r + 1, ux_ = lx + 1;
+      const int py = uy_ + 2, px = ux_ + 2;
+      const NodeState& n = ns[r];
+      const double phid = s.phi[py][px];
+      // div(phi u) with the ghost velocity 2 u_w - u(mirror) beyond a wall (A9)
+      double dq = 0.0;
+#pragma unroll
+      for (int i = 1; i < 9; ++i) {
+        int qy = uy_ + cy(i), qx = ux_ + cx(i);
+        const int nxg = x + cx(i), nyg = y + cy(i);
+        bool gx_ = false, gy_ = false;
+        double uwx = 0.0, uwy = 0.0;
+        if (c.wall_x && (nxg < 0 || nxg >= g.nx)) { gx_ = true; qx = ux_; uwy = nxg < 0 ? c.uw_lo_d : c.uw_hi_d; }
+        if (c.wall_y && (nyg < 0 || nyg >= g.ny)) { gy_ = true; qy = uy_; uwx = nyg < 0 ? c.uw_lo_d : c.uw_hi_d; }
+        double vx = (qx == ux_ && qy == uy_) ? n.ux : (double)s.u[0][qy][qx];
+        double vy = (qx == ux_ && qy == uy_) ? n.uy : (double)s.u[1][qy][qx];
+        if (gx_) { vx = -vx; vy = 2.0 * uwy - vy; }
+        if (gy_) { vx = 2.0 * uwx - vx; vy = -vy; }
+        const double ph = s.phi[py + cy(i)][px + cx(i)];
+        dq += wtd(i) * ((double)cx(i) * (ph * vx) + (double)cy(i) * (ph * vy));
+      }
+      dq *= 3.0;
+      const long long o = (long long)y * g.pitch + x;
+      const double qx = phid * n.ux, qy = phid * n.uy;
+      const double dtx = qx - (double)a.J[o], dty = qy - (double)a.J[g.ps + o];   // explicit-Euler d_t(phi u) (A4)
+      a.J[o] = (float)qx;
+      a.J[g.ps + o] = (float)qy;
+      a.pout[o] = n.Pn;
+
+      if (!(isfinite(n.ux) && isfinite(n.uy) && isfinite(phid))) atomicOr(a.status, 1);
+
+      const double tau_f = 0.5 + 3.0 * mu_of(phid, c) / n.rho;   // A6
+      const double omf = 1.0 / tau_f, cff = 1.0 - 0.5 * omf;
+      const double omh = c.inv_tau_h_d, cfh = 1.0 - 0.5 * omh;
+      const double usq = n.ux * n.ux + n.uy * n.uy;
+      const double cs2rho = n.rho / 3.0;
+      const double dPn = n.P - (double)n.Pn;
+
+      // pulled h_i (i >= 1); h_0 - phi = -sum_{i>=1} h_i
+      float h[9];
+      const int wx = c.wall_x, wy = c.wall_y;
+      h[1] = pull<1>(a.hin, x, y, g, wx, wy);
+      h[2] = pull<2>(a.hin, x, y, g, wx, wy);
+      h[3] = pull<3>(a.hin, x, y, g, wx, wy);
+      h[4] = pull<4>(a.hin, x, y, g, wx, wy);
+      h[5] = pull<5>(a.hin, x, y, g, wx, wy);
+      h[6] = pull<6>(a.hin, x, y, g, wx, wy);
+      h[7] = pull<7>(a.hin, x, y, g, wx, wy);
+      h[8] = pull<8>(a.hin, x, y, g, wx, wy);
+      const double etamu = c.eta_d * n.mu;
+      const double hsrc = c.a_h_d * dq;
+      double d0sum = 0.0;   // sum of the stored h_i^+ (i >= 1)
+
+#pragma unroll
+      for (int i = 1; i < 9; ++i) {
+        const double cu = (double)cx(i) * n.ux + (double)cy(i) * n.uy;
+        const double si = 3.0 * cu + 4.5 * cu * cu - 1.5 * usq;      // s_i(u), Eq. (33)
+        const double heq = wtd(i) * etamu + wtd(i) * phid * 3.0 * cu;   // Eq. (32)
+        const double Hi = wtd(i) * hsrc + wtd(i) * 3.0 * ((double)cx(i) * dtx + (double)cy(i) * dty);   // Eq. (36)
+        double hp = (double)h[i] - ((double)h[i] - heq) * omh + cfh * Hi;   // Eq. (30)
+        // Eq. (43): a population about to cross a wall is stored in its own
+        // slot with the moving-wall term; the next pull reads it as opp(i).
+        const int tx = x + cx(i), tyy = y + cy(i);
+        double cuw = 0.0;
+        bool hit = false;
+        if (c.wall_x && (tx < 0 || tx >= g.nx)) { hit = true; cuw = (double)cy(i) * (tx < 0 ? c.uw_lo_d : c.uw_hi_d); }
+        if (c.wall_y && (tyy < 0 || tyy >= g.ny)) { hit = true; cuw = (double)cx(i) * (tyy < 0 ? c.uw_lo_d : c.uw_hi_d); }
+        if (hit) hp -= 6.0 * wtd(i) * phid * cuw;
+        const float hs = (float)hp;
+        d0sum += (double)hs;
+        a.hout[(long long)i * g.ps + o] = hs;
+        (void)si;
+      }
+      // slot 0 holds d0 = h_0^+ - phi.  The collision conserves sum_i h_i = phi
+      // (Eqs. 32 and 36), so d0 = -sum_{i>=1} h_i^+ exactly; forming it from
+      // the stored values makes the update of phi conservative.
+      a.hout[o] = (float)(-d0sum);
+
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        const double cu = (double)cx(i) * n.ux + (double)cy(i) * n.uy;
+        const double si = 3.0 * cu + 4.5 * cu * cu - 1.5 * usq;      // s_i(u), Eq. (33)
+        const double feq = wtd(i) * (dPn + cs2rho * si);              // f_i^eq - w_i Pn, Eq. (31)
+        const double gam = wtd(i) * (1.0 + si);                       // Gamma_i (A1)
+        const double Fi = ((double)cx(i) - n.ux) * (gam * n.fx + wtd(i) * si * (1.0 / 3.0) * n.grx) +
+                          ((double)cy(i) - n.uy) * (gam * n.fy + wtd(i) * si * (1.0 / 3.0) * n.gry);   // Eq. (35)
+        const double fi = (double)n.f[i];
+        double fp = fi - (fi - feq) * omf + cff * Fi;                 // Eq. (29), minus w_i Pn
+        if (i != 0) {
+          const int tx = x + cx(i), tyy = y + cy(i);
+          double cuw = 0.0;
+          bool hit = false;
+          if (c.wall_x && (tx < 0 || tx >= g.nx)) { hit = true; cuw = (double)cy(i) * (tx < 0 ? c.uw_lo_d : c.uw_hi_d); }
+          if (c.wall_y && (tyy < 0 || tyy >= g.ny)) { hit = true; cuw = (double)cx(i) * (tyy < 0 ? c.uw_lo_d : c.uw_hi_d); }
+          if (hit) fp -= 2.0 * wtd(i) * n.rho * cuw;
+        }
+        a.fout[(long long)i * g.ps + o] = (float)fp;
+      }
+    }
+  }
+}
+
+// phi^{n+1}(x) = phi^n(x) + d0(x) + sum_{i>=1} h_i^+(x - c_i)   (Eq. 37, phi = sum h_i)
+__global__ __launch_bounds__(256) void k_phi(const float* __restrict__ h, double* __restrict__ phi, Grid g, int wx,
+                                             int wy) {
+  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (x >= g.nx || y >= g.ny) return;
+  const long long o = (long long)y * g.pitch + x;
+  double s = (double)h[o];
+  s += (double)pull<1>(h, x, y, g, wx, wy);
+  s += (double)pull<2>(h, x, y, g, wx, wy);
+  s += (double)pull<3>(h, x, y, g, wx, wy);
+  s += (double)pull<4>(h, x, y, g, wx, wy);
+  s += (double)pull<5>(h, x, y, g, wx, wy);
+  s += (double)pull<6>(h, x, y, g, wx, wy);
+  s += (double)pull<7>(h, x, y, g, wx, wy);
+  s += (double)pull<8>(h, x, y, g, wx, wy);
+  phi[o] += s;
+}
+
+// Initial state, pass 1: node-local f^eq(P = 0, rho(phi0), u0) and
+// h^eq(phi0, mu(phi0), u0) (Eqs. 31-32; reading A11), phi (FP64), J = phi0 u0.
+__global__ __launch_bounds__(256) void k_init_local(const float* __restrict__ phi0, const float* __restrict__ ux0,
+                                                    const float* __restrict__ uy0, float* __restrict__ ft,
+                                                    float* __restrict__ ht, float* __restrict__ J,
+                                                    double* __restrict__ phi, float* __restrict__ P, Grid g, Phys c) {
+  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (x >= g.nx || y >= g.ny) return;
+  const long long o = (long long)y * g.pitch + x;
+  const double p0 = (double)phi0[(long long)y * g.nx + x];
+  double sl = 0.0;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const int sx = wrap_or_reflect(x + cx(i), g.nx, c.wall_x), sy = wrap_or_reflect(y + cy(i), g.ny, c.wall_y);
+    sl += wtd(i) * ((double)phi0[(long long)sy * g.nx + sx] - p0);
+  }
+  const float lap = (float)(6.0 * sl);
+  const float mu = c.beta4 * (float)p0 * (float)((p0 - 1.0) * (p0 + 1.0)) - c.kappa * lap;
+  const float ux = ux0 ? ux0[(long long)y * g.nx + x] : 0.f;
+  const float uy = uy0 ? uy0[(long long)y * g.nx + x] : 0.f;
+  const float rho = rho_of(p0, c);
+  const float usq = ux * ux + uy * uy;
+  const float etamu = c.eta * mu;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const float cu = (float)cx(i) * ux + (float)cy(i) * uy;
+    const float si = 3.0f * cu + 4.5f * cu * cu - 1.5f * usq;
+    ft[(long long)i * g.ps + o] = wt(i) * CS2 * rho * si;
+    ht[(long long)i * g.ps + o] = (i == 0) ? 0.0f : wt(i) * etamu + wt(i) * (float)p0 * 3.0f * cu;
+  }
+  phi[o] = p0;
+  P[o] = 0.0f;   // P0 = 0: the stored f are then f itself
+  J[o] = (float)p0 * ux;
+  J[g.ps + o] = (float)p0 * uy;
+}
+
+// Initial state, pass 2: place node-local populations in the stored (post-
+// collision) layout so that the pull of the first step returns them:
+// slot j at y holds the value of node y + c_j, or the opp(j) value of y itself
+// when y + c_j lies beyond a wall.
+__global__ __launch_bounds__(256) void k_init_unstream(const float* __restrict__ ft, const float* __restrict__ ht,
+                                                       float* __restrict__ f, float* __restrict__ h, Grid g, int wx,
+                                                       int wy) {
+  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (x >= g.nx || y >= g.ny) return;
+  const long long o = (long long)y * g.pitch + x;
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    int tx = x + cx(j), ty = y + cy(j);
+    bool out = false;
+    if (wx) out |= (tx < 0) | (tx >= g.nx); else tx = (tx + g.nx) % g.nx;
+    if (wy) out |= (ty < 0) | (ty >= g.ny); else ty = (ty + g.ny) % g.ny;
+    long long src = out ? (long long)opp(j) * g.ps + o : (long long)j * g.ps + (long long)ty * g.pitch + tx;
+    f[(long long)j * g.ps + o] = ft[src];
+    h[(long long)j * g.ps + o] = (j == 0) ? 0.0f : ht[src];
+  }
+}
+
+// Deterministic sum of the phi plane: per-block partial sums, then one block.
+__global__ __launch_bounds__(256) void k_sum_partial(const double* __restrict__ phi, Grid g, double* partial) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  const long long n = (long long)g.nx * g.ny;
+  for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < n; k += (long long)gridDim.x * 256) {
+    const long long y = k / g.nx, x = k - y * g.nx;
+    acc += phi[y * g.pitch + x];
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum_final(const double* __restrict__ partial, int n, double* out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < n; k += 256) acc += partial[k];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+__global__ void k_fill_int(int* p, int v, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = v;
+}
+
+template <int FORM>
+hipError_t launch_fused_t(const StepArgs& a, const MomentArgs& m, bool moments, hipStream_t st) {
+  dim3 grid((a.g.nx + kTX - 1) / kTX, (a.g.ny + kTY - 1) / kTY);
+  if (moments) hipLaunchKernelGGL((k_fused<FORM, true>), grid, dim3(kThreads), 0, st, a, m);
+  else hipLaunchKernelGGL((k_fused<FORM, false>), grid, dim3(kThreads), 0, st, a, m);
+  return hipGetLastError();
+}
+
+hipError_t dispatch(int form, const StepArgs& a, const MomentArgs& m, bool moments, hipStream_t st) {
+  switch (form) {
+    case 0: return launch_fused_t<0>(a, m, moments, st);
+    case 1: return launch_fused_t<1>(a, m, moments, st);
+    case 2: return launch_fused_t<2>(a, m, moments, st);
+    case 3: return launch_fused_t<3>(a, m, moments, st);
+    case 4: return launch_fused_t<4>(a, m, moments, st);
+    case 5: return launch_fused_t<5>(a, m, moments, st);
+    case 6: return launch_fused_t<6>(a, m, moments, st);
+    case 7: return launch_fused_t<7>(a, m, moments, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_fused(int form, const StepArgs& a, hipStream_t s) { return dispatch(form, a, MomentArgs{}, false, s); }
+
+hipError_t launch_moments(int form, const StepArgs& a, const MomentArgs& m, hipStream_t s) {
+  return dispatch(form, a, m, true, s);
+}
+
+hipError_t launch_phi(const float* h, double* phi, const Grid& g, int wall_x, int wall_y, hipStream_t s) {
+  dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4);
+  hipLaunchKernelGGL(k_phi, grid, dim3(256), 0, s, h, phi, g, wall_x, wall_y);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(const float* phi0, const float* ux0, const float* uy0, float* f_tmp, float* h_tmp, float* f_out,
+                       float* h_out, float* J, double* phi, float* P, const Grid& g, const Phys& c, hipStream_t s) {
+  dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4);
+  hipLaunchKernelGGL(k_init_local, grid, dim3(256), 0, s, phi0, ux0, uy0, f_tmp, h_tmp, J, phi, P, g, c);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_init_unstream, grid, dim3(256), 0, s, f_tmp, h_tmp, f_out, h_out, g, c.wall_x, c.wall_y);
+  return hipGetLastError();
+}
+
+hipError_t launch_phi_sum(const double* phi, const Grid& g, double* partial, int npartial, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_partial, dim3(npartial), dim3(256), 0, s, phi, g, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, partial, npartial, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int* p, int value, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, s, p, value, n);
+  return hipGetLastError();
+}
+
+}  // namespace pflbm

@@ -1,0 +1,128 @@
+"""GPU checks that hold at any size: conservation, rest state, symmetry,
+checkpoint/restore, divergence detection, and one-step parity at the full
+benchmark sizes (2048x2048 droplet, 1024x4096 channel)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as WL
+from oracle import lbm_ref as R
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def sim_of(p, phi0, ux0=None, uy0=None):
+    import paper_2012_14729_amd as P
+    return P.Simulation(p.as_dict(), np.asarray(phi0, np.float32), ux0, uy0)
+
+
+@pytest.mark.parametrize("form", ["stf1", "cpf2", "csf2"])
+def test_order_parameter_conserved(form):
+    p, phi0, ux0, uy0 = WL.config_shear(nx=128, ny=64, R=16.0)
+    s = sim_of(p, phi0, ux0, uy0)
+    s0 = float(np.asarray(phi0, np.float32).astype(np.float64).sum())
+    s.step(500, form)
+    phi = s.moments(form)["phi"].double()
+    # phi moments are FP32 copies of the FP64 state: allow their rounding only
+    assert abs(float(phi.sum()) - s0) < 1e-7 * phi.numel()
+
+
+def test_rest_state_stays_at_rest():
+    p = WL.ParamSet(nx=64, ny=16, rho1=4.0, rho2=1.0, sigma=0.02)
+    s = sim_of(p, np.full((16, 64), 0.3))
+    for form in ("stf1", "stf2", "cpf1", "cpf2", "pf1", "pf2", "csf1", "csf2"):
+        s.step(5, form)
+        m = s.moments(form)
+        assert float(m["ux"].abs().max()) == 0.0 and float(m["uy"].abs().max()) == 0.0
+        assert float(m["P"].abs().max()) == 0.0
+
+
+def test_transpose_symmetry():
+    """x <-> y swap of the input swaps the output (square periodic grid)."""
+    p = WL.ParamSet(nx=64, ny=64, rho1=10.0, rho2=1.0, sigma=0.01, W=4.0)
+    phi0 = WL.droplet(64, 64, 12.0, 4.0, xc=27.3, yc=35.9).astype(np.float32)
+    a = sim_of(p, phi0)
+    b = sim_of(p, phi0.T.copy())
+    a.step(50, "stf2")
+    b.step(50, "stf2")
+    ma, mb = a.moments("stf2"), b.moments("stf2")
+    umax = float(torch.sqrt(ma["ux"] ** 2 + ma["uy"] ** 2).max())
+    assert float((ma["phi"].T - mb["phi"]).abs().max()) < 1e-6
+    assert float((ma["ux"].T - mb["uy"]).abs().max()) < 1e-4 * umax
+
+
+def test_checkpoint_restore_bitwise():
+    p, phi0, ux0, uy0 = WL.config_shear(nx=64, ny=32, R=8.0)
+    s = sim_of(p, phi0, ux0, uy0)
+    s.step(20, "csf1")
+    blob = s.save()
+    s.step(30, "csf1")
+    a = {k: v.clone() for k, v in s.moments("csf1").items()}
+    s.restore(blob)
+    s.step(30, "csf1")
+    b = s.moments("csf1")
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
+
+
+def test_divergence_is_reported():
+    p = WL.ParamSet(nx=64, ny=16, sigma=0.01)
+    phi0 = np.zeros((16, 64), np.float32)
+    phi0[3, 7] = np.nan          # non-finite input set on the host
+    s = sim_of(p, phi0)
+    s.step(3, "cpf2")
+    assert s.status() is True
+    ok = sim_of(p, np.zeros((16, 64), np.float32))
+    ok.step(3, "cpf2")
+    assert ok.status() is False
+
+
+def test_zero_steps_and_timing():
+    p, phi0, _, _ = WL.config_droplet64()
+    s = sim_of(p, phi0)
+    m0 = {k: v.clone() for k, v in s.moments("cpf2").items()}
+    s.step(0, "cpf2")
+    assert torch.equal(m0["ux"], s.moments("cpf2")["ux"])
+    s.set_timing(True)
+    s.step(7, "cpf2")
+    ms, n = s.kernel_time(0)
+    assert n == 7 and ms > 0
+    ms1, n1 = s.kernel_time(1)
+    assert n1 == 7 and ms1 > 0
+    assert s.step_count == 7
+
+
+def _one_step_full_size(p, phi0, form):
+    op = R.Params(**{k: (None if k == "rho0" and math.isnan(v) else v) for k, v in p.as_dict().items()})
+    phi32 = np.asarray(phi0, np.float32)
+    print(f"[full-size] {p.nx}x{p.ny} form={form}: oracle one step", flush=True)
+    st = R.step(R.init(op, torch.tensor(phi32, dtype=torch.float64)), form, op)
+    ref = {k: v.numpy() for k, v in R.moments(st, form, op).items()}
+    s = sim_of(p, phi32)
+    s.step(1, form)
+    got = {k: v.cpu().numpy().astype(np.float64) for k, v in s.moments(form).items()}
+    for k in ("phi", "rho"):
+        assert np.abs(got[k] - ref[k]).max() / np.abs(ref[k]).max() < 1e-6, k
+    umax = np.sqrt(ref["ux"] ** 2 + ref["uy"] ** 2).max()
+    eu = max(np.abs(got["ux"] - ref["ux"]).max(), np.abs(got["uy"] - ref["uy"]).max()) / umax
+    assert eu < 1e-5, eu
+
+
+def test_full_size_droplet_one_step():
+    """2048x2048 droplet (density ratio 1000), the benchmark launch shape."""
+    p, phi0, _, _ = WL.config_droplet_large(2048)
+    _one_step_full_size(p, phi0, "stf1")
+
+
+def test_full_size_channel_one_step():
+    """1024x4096 bubble between x-walls with gravity."""
+    p, phi0, _, _ = WL.config_bubble()
+    _one_step_full_size(p, phi0, "stf2")
