@@ -38,7 +38,8 @@ bool finite(double v) { return std::isfinite(v); }
 int validate(const lbm_params* p) {
   if (!p) return fail(LBM_E_INVAL, "params is NULL");
   if (p->nx < 8 || p->ny < 8) return fail(LBM_E_INVAL, "nx, ny must be >= 8 (got %d, %d)", p->nx, p->ny);
-  if ((long long)p->nx * p->ny > (1LL << 31)) return fail(LBM_E_INVAL, "grid too large");
+  if (9LL * (((long long)p->nx + 63) / 64 * 64) * p->ny >= (1LL << 31))
+    return fail(LBM_E_INVAL, "grid too large (9 planes must hold fewer than 2^31 elements)");
   if ((p->wall_x != 0 && p->wall_x != 1) || (p->wall_y != 0 && p->wall_y != 1))
     return fail(LBM_E_INVAL, "wall_x, wall_y must be 0 or 1");
   if (p->wall_x && p->wall_y && (p->u_wall_lo != 0.0 || p->u_wall_hi != 0.0))
@@ -115,6 +116,7 @@ Layout layout_for(const lbm_params* p) {
   L.g.ny = p->ny;
   L.g.pitch = (int)align_up((size_t)p->nx, 64);
   L.g.ps = (long long)L.g.pitch * p->ny;
+  L.g.psi = (int)L.g.ps;
   const size_t plane = (size_t)L.g.ps * sizeof(float);
   size_t o = 0;
   for (int b = 0; b < 2; ++b) { L.off_f[b] = o; o = align_up(o + 9 * plane, kAlign); }

@@ -49,6 +49,7 @@ struct Phys {
 struct Grid {
   int nx, ny, pitch;
   long long ps;           // plane stride in elements
+  int psi;                // the same as int (9 * ps < 2^31 is validated)
 };
 
 struct StepArgs {

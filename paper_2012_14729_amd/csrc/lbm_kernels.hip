@@ -23,6 +23,7 @@ constexpr int BW = kTX + 4, BH = kTY + 4;   // second-level fields (halo 2)
 constexpr int UW = kTX + 2, UH = kTY + 2;   // velocity ring (halo 1)
 constexpr int NRING = 2 * UW + 2 * kTY;     // positions of the velocity ring
 constexpr float CS2 = 1.0f / 3.0f;
+constexpr int kFusedThreads = kTX * kTY;   // one node per thread
 
 __device__ __forceinline__ int wrap_or_reflect(int c, int n, int wall) {
   if (wall) {
@@ -34,41 +35,41 @@ __device__ __forceinline__ int wrap_or_reflect(int c, int n, int wall) {
   return c < 0 ? c + n : c;
 }
 
-// Pull population i for node (x, y) (x, y inside the domain): the value that
-// left x - c_i in direction i; if x - c_i lies beyond a wall the slot opp(i)
-// of x itself holds the bounced population (wall term applied at store time).
+// Source of the pulled population i for node (x, y) inside the domain: the
+// value that left x - c_i in direction i; if x - c_i lies beyond a wall the
+// slot opp(i) of x itself holds the bounced population (the wall term is
+// applied when it is stored).  Returns the node offset; `slot` the plane.
+// Offsets are 32-bit: a simulation holds fewer than 2^31 elements per buffer.
 template <int I>
-__device__ __forceinline__ float pull(const float* __restrict__ base, int x, int y, const Grid& g, int wx, int wy) {
+__device__ __forceinline__ int src_off(int x, int y, const Grid& g, int wx, int wy, int& slot) {
   int sx = x - cx(I), sy = y - cy(I);
   bool bounce = false;
   if (cx(I) != 0) {
     if (wx) bounce |= (sx < 0) | (sx >= g.nx);
-    else sx = sx < 0 ? sx + g.nx : (sx >= g.nx ? sx - g.nx : sx);
+    sx = sx < 0 ? sx + g.nx : (sx >= g.nx ? sx - g.nx : sx);
   }
   if (cy(I) != 0) {
     if (wy) bounce |= (sy < 0) | (sy >= g.ny);
-    else sy = sy < 0 ? sy + g.ny : (sy >= g.ny ? sy - g.ny : sy);
-  }
-  if (bounce) return base[(long long)opp(I) * g.ps + (long long)y * g.pitch + x];
-  return base[(long long)I * g.ps + (long long)sy * g.pitch + sx];
-}
-
-// Source of the pulled population i for node (x, y): the offset of the node
-// it is read from and the slot, following the same rule as pull<I>.
-template <int I>
-__device__ __forceinline__ long long src_off(int x, int y, const Grid& g, int wx, int wy, int& slot) {
-  int sx = x - cx(I), sy = y - cy(I);
-  bool bounce = false;
-  if (cx(I) != 0) {
-    if (wx) bounce |= (sx < 0) | (sx >= g.nx);
-    else sx = sx < 0 ? sx + g.nx : (sx >= g.nx ? sx - g.nx : sx);
-  }
-  if (cy(I) != 0) {
-    if (wy) bounce |= (sy < 0) | (sy >= g.ny);
-    else sy = sy < 0 ? sy + g.ny : (sy >= g.ny ? sy - g.ny : sy);
+    sy = sy < 0 ? sy + g.ny : (sy >= g.ny ? sy - g.ny : sy);
   }
   slot = bounce ? opp(I) : I;
-  return bounce ? (long long)y * g.pitch + x : (long long)sy * g.pitch + sx;
+  return bounce ? y * g.pitch + x : sy * g.pitch + sx;
+}
+
+template <int I>
+__device__ __forceinline__ float pull(const float* __restrict__ base, int x, int y, const Grid& g, int wx, int wy) {
+  int sl;
+  const int o = src_off<I>(x, y, g, wx, wy, sl);
+  return base[(unsigned)(sl * g.psi + o)];
+}
+
+// 1/x in FP64 from an FP32 seed and two Newton steps (exact to ~1 ulp for
+// the positive, normal arguments used here: densities, relaxation times).
+__device__ __forceinline__ double rcp64(double x) {
+  double r = (double)__frcp_rn((float)x);
+  r = r * (2.0 - x * r);
+  r = r * (2.0 - x * r);
+  return r;
 }
 
 // Mixture density and viscosity (Eqs. 9-10) from the FP64 order parameter,
@@ -80,7 +81,7 @@ __device__ __forceinline__ double mu_of(double phi, const Phys& c) { return c.mu
 struct Lds {
   double phi[PH][PW];
   double b[3][BH][BW];
-  float u[2][UH][UW];
+  float q[2][UH][UW];   // phi u on the tile and its 1-node ring
 };
 
 // gradient and Laplacian of phi at sPhi position (py, px) (Eqs. 41-42), in
@@ -125,7 +126,7 @@ template <int FORM>
 __device__ __forceinline__ void stage_b(Lds& s, int tid, const Phys& c) {
   if constexpr (FORM == 3 || FORM == 4) return;   // CPF-2, PF-1: pointwise at radius 1
   const double kappa = c.kappa_d;
-  for (int k = tid; k < BH * BW; k += kThreads) {
+  for (int k = tid; k < BH * BW; k += kFusedThreads) {
     const int by = k / BW, bx = k - by * BW;
     const int py = by + 1, px = bx + 1;
     double gx, gy, lap;
@@ -222,34 +223,38 @@ __device__ __forceinline__ void force_sf(const Lds& s, int uy_, int ux_, const P
 // pressure: f[i] = f_i - w_i Pn.
 struct NodeState {
   float f[9];
-  float Pn;
-  double ux, uy, fx, fy, rho, P, grx, gry, mu;
+  float Pn, fx, fy, grx, gry, mu;
+  double ux, uy, rho, P;
 };
 
-#define PULL_FP(I)                                                \
-  {                                                               \
-    int sl_;                                                      \
-    const long long o_ = src_off<I>(x, y, a.g, wx, wy, sl_);      \
-    ft[I] = a.fin[(long long)sl_ * a.g.ps + o_];                  \
-    ps[I] = a.pin[o_];                                            \
+// Pull the stored flow populations and the pressures of their source nodes
+// for node (x, y) inside the domain (Eqs. 29 and 43, pull form).
+__device__ __forceinline__ void load_fp(const StepArgs& a, int x, int y, float* ft, float* ps) {
+  const int wx = a.c.wall_x, wy = a.c.wall_y;
+#define PULL_FP(I)                                               \
+  {                                                              \
+    int sl_;                                                     \
+    const int o_ = src_off<I>(x, y, a.g, wx, wy, sl_);           \
+    ft[I] = a.fin[(unsigned)(sl_ * a.g.psi + o_)];               \
+    ps[I] = a.pin[(unsigned)o_];                                 \
   }
+  PULL_FP(0) PULL_FP(1) PULL_FP(2) PULL_FP(3) PULL_FP(4) PULL_FP(5) PULL_FP(6) PULL_FP(7) PULL_FP(8)
+#undef PULL_FP
+}
 
 // Velocity (and, for active nodes, the rest of Eq. 37) at a node whose
-// velocity-ring position is (uy_, ux_) and global position (x, y) inside the
-// domain.  The stored flow populations are deviations from the pressure of
-// the node that stored them: f_i = ft_i + w_i ps_i.
+// velocity-ring position is (uy_, ux_).  The stored flow populations are
+// deviations from the pressure of the node that stored them:
+// f_i = ft_i + w_i ps_i.
 template <int FORM, bool FULL>
-__device__ __forceinline__ void velocity_at(const Lds& s, const StepArgs& a, int uy_, int ux_, int x, int y,
-                                            NodeState& ns) {
+__device__ __forceinline__ void velocity_from(const Lds& s, const StepArgs& a, int uy_, int ux_, const float* ft,
+                                              const float* ps, NodeState& ns) {
   double fx, fy;
   force_sf<FORM>(s, uy_, ux_, a.c, fx, fy);
   const double phid = s.phi[uy_ + 2][ux_ + 2];
   const double rho = rho_of(phid, a.c);
   fx += (rho - a.c.rho0_d) * a.c.gx_d;   // F_g = (rho - rho0) g   (Eq. 8)
   fy += (rho - a.c.rho0_d) * a.c.gy_d;
-  const int wx = a.c.wall_x, wy = a.c.wall_y;
-  float ft[9], ps[9];
-  PULL_FP(0) PULL_FP(1) PULL_FP(2) PULL_FP(3) PULL_FP(4) PULL_FP(5) PULL_FP(6) PULL_FP(7) PULL_FP(8)
   double jx = 0.0, jy = 0.0;
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
@@ -257,7 +262,7 @@ __device__ __forceinline__ void velocity_at(const Lds& s, const StepArgs& a, int
     if (cx(i) != 0) jx += cx(i) * fi;
     if (cy(i) != 0) jy += cy(i) * fi;
   }
-  const double inv_rho = 1.0 / rho;
+  const double inv_rho = rcp64(rho);
   const double ux = (3.0 * jx + 0.5 * fx) * inv_rho;   // Eq. (37)
   const double uy = (3.0 * jy + 0.5 * fy) * inv_rho;
   ns.ux = ux;
@@ -265,16 +270,17 @@ __device__ __forceinline__ void velocity_at(const Lds& s, const StepArgs& a, int
   if constexpr (FULL) {
     double gx, gy, lap;
     grad_lap_phi(s, uy_ + 2, ux_ + 2, gx, gy, lap);
-    ns.fx = fx;
-    ns.fy = fy;
+    const double grx = a.c.drho_half_d * gx, gry = a.c.drho_half_d * gy;   // grad rho = (rho1 - rho2)/2 grad phi
+    ns.fx = (float)fx;
+    ns.fy = (float)fy;
     ns.rho = rho;
-    ns.grx = a.c.drho_half_d * gx;   // grad rho = (rho1 - rho2)/2 grad phi
-    ns.gry = a.c.drho_half_d * gy;
-    ns.mu = chem_pot(phid, lap, a.c);
+    ns.grx = (float)grx;
+    ns.gry = (float)gry;
+    ns.mu = (float)chem_pot(phid, lap, a.c);
     double sumf = 0.0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) sumf += (double)ft[i] + wtd(i) * (double)ps[i];
-    const double P = sumf + (ux * ns.grx + uy * ns.gry) * (0.5 / 3.0);   // Eq. (37)
+    const double P = sumf + (ux * grx + uy * gry) * (0.5 / 3.0);   // Eq. (37)
     const float Pn = (float)P;
     ns.P = P;
     ns.Pn = Pn;
@@ -306,115 +312,98 @@ __device__ __forceinline__ bool ring_global(int uy_, int ux_, int x0, int y0, co
 }
 
 template <int FORM, bool MOMENTS>
-__global__ __launch_bounds__(kThreads) void k_fused(StepArgs a, MomentArgs m) {
+__global__ __launch_bounds__(kFusedThreads) void k_fused(StepArgs a, MomentArgs m) {
   __shared__ Lds s;
   const int tid = threadIdx.x;
   const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY;
-  const int lx = tid & (kTX - 1), ty = tid >> 6;   // column, first row (rows ty, ty + 4)
+  const int lx = tid & (kTX - 1), ty = tid / kTX;   // one node per thread
   const Grid& g = a.g;
+  const Phys& c = a.c;
+  const int uy_ = ty + 1, ux_ = lx + 1;             // velocity-ring coordinates of this node
+  int x, y;
+  const bool valid = ring_global(uy_, ux_, x0, y0, a, x, y);
+  const bool act = (x0 + lx < g.nx) && (y0 + ty < g.ny);
 
+  // This node's HBM reads are issued first so they complete while the LDS
+  // stencil stages run.
+  float ft[9], ps[9], h[9];
+  float j0 = 0.f, j1 = 0.f;
+  if (valid) load_fp(a, x, y, ft, ps);
   // Stage A: phi tile with a 3-node halo (periodic wrap / even reflection at walls, Sec. IV)
-  for (int k = tid; k < PH * PW; k += kThreads) {
+  for (int k = tid; k < PH * PW; k += kFusedThreads) {
     const int py = k / PW, px = k - py * PW;
-    const int gx = wrap_or_reflect(x0 + px - 3, g.nx, a.c.wall_x);
-    const int gy = wrap_or_reflect(y0 + py - 3, g.ny, a.c.wall_y);
-    s.phi[py][px] = a.phi[(long long)gy * g.pitch + gx];
+    const int gx = wrap_or_reflect(x0 + px - 3, g.nx, c.wall_x);
+    const int gy = wrap_or_reflect(y0 + py - 3, g.ny, c.wall_y);
+    s.phi[py][px] = a.phi[(unsigned)(gy * g.pitch + gx)];
   }
   __syncthreads();
 
-  stage_b<FORM>(s, tid, a.c);
+  stage_b<FORM>(s, tid, c);
   __syncthreads();
 
-  // Stage C: velocity (and moments) on the tile and, for the step, its ring.
-  NodeState ns[2];
-  bool act[2];
-  int gxs[2], gys[2];
-#pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const int uy_ = ty + 4 * r + 1, ux_ = lx + 1;
-    int x, y;
-    const bool valid = ring_global(uy_, ux_, x0, y0, a, x, y);
-    act[r] = (x0 + lx < g.nx) && (y0 + ty + 4 * r < g.ny);
-    gxs[r] = x;
-    gys[r] = y;
-    if (valid) {
-      velocity_at<FORM, true>(s, a, uy_, ux_, x, y, ns[r]);
-      if constexpr (!MOMENTS) {
-        s.u[0][uy_][ux_] = (float)ns[r].ux;
-        s.u[1][uy_][ux_] = (float)ns[r].uy;
+  // Stage C: velocities of the ring (step only), then of this node.
+  if constexpr (!MOMENTS) {
+    if (tid < NRING) {
+      int ruy, rux, rx, ry;
+      ring_pos(tid, ruy, rux);
+      if (ring_global(ruy, rux, x0, y0, a, rx, ry)) {
+        float rft[9], rps[9];
+        load_fp(a, rx, ry, rft, rps);
+        NodeState rs;
+        velocity_from<FORM, false>(s, a, ruy, rux, rft, rps, rs);
+        const double ph = s.phi[ruy + 2][rux + 2];
+        s.q[0][ruy][rux] = (float)(ph * rs.ux);
+        s.q[1][ruy][rux] = (float)(ph * rs.uy);
       }
+    }
+  }
+  NodeState n;
+  if (valid) {
+    velocity_from<FORM, true>(s, a, uy_, ux_, ft, ps, n);
+    if constexpr (!MOMENTS) {
+      const double ph = s.phi[uy_ + 2][ux_ + 2];
+      s.q[0][uy_][ux_] = (float)(ph * n.ux);
+      s.q[1][uy_][ux_] = (float)(ph * n.uy);
     }
   }
   if constexpr (MOMENTS) {
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      if (!act[r]) continue;
-      const long long o = (long long)gys[r] * g.nx + gxs[r];
-      if (m.phi) m.phi[o] = (float)s.phi[ty + 4 * r + 3][lx + 3];
-      if (m.rho) m.rho[o] = (float)ns[r].rho;
-      if (m.ux) m.ux[o] = (float)ns[r].ux;
-      if (m.uy) m.uy[o] = (float)ns[r].uy;
-      if (m.p) m.p[o] = (float)ns[r].P;
+    if (act) {
+      const long long o = (long long)y * g.nx + x;
+      if (m.phi) m.phi[o] = (float)s.phi[ty + 3][lx + 3];
+      if (m.rho) m.rho[o] = (float)n.rho;
+      if (m.ux) m.ux[o] = (float)n.ux;
+      if (m.uy) m.uy[o] = (float)n.uy;
+      if (m.p) m.p[o] = (float)n.P;
     }
     return;
   } else {
-    if (tid < NRING) {
-      int uy_, ux_, x, y;
-      ring_pos(tid, uy_, ux_);
-      if (ring_global(uy_, ux_, x0, y0, a, x, y)) {
-        NodeState rs;
-        velocity_at<FORM, false>(s, a, uy_, ux_, x, y, rs);
-        s.u[0][uy_][ux_] = (float)rs.ux;
-        s.u[1][uy_][ux_] = (float)rs.uy;
-      }
-    }
     __syncthreads();
+    if (!act) return;
 
-    const Phys& c = a.c;
+    const int py = uy_ + 2, px = ux_ + 2;
+    const double phid = s.phi[py][px];
+    // div(phi u) (Eq. 41) from the node field q = phi u; beyond a wall the
+    // ghost velocity is 2 u_w - u(mirror) with phi mirrored (A9), i.e.
+    // q_ghost = 2 u_w phi(mirror) - q(mirror) along the wall, -q(mirror) across.
+    float dqf = 0.f;
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      if (!act[r]) continue;
-      const int x = gxs[r], y = gys[r];
-      const int uy_ = ty + 4 * r + 1, ux_ = lx + 1;
-      const int py = uy_ + 2, px = ux_ + 2;
-      const NodeState& n = ns[r];
-      const double phid = s.phi[py][px];
-      // div(phi u) with the ghost velocity 2 u_w - u(mirror) beyond a wall (A9)
-      double dq = 0.0;
-#pragma unroll
-      for (int i = 1; i < 9; ++i) {
-        int qy = uy_ + cy(i), qx = ux_ + cx(i);
-        const int nxg = x + cx(i), nyg = y + cy(i);
-        bool gx_ = false, gy_ = false;
-        double uwx = 0.0, uwy = 0.0;
-        if (c.wall_x && (nxg < 0 || nxg >= g.nx)) { gx_ = true; qx = ux_; uwy = nxg < 0 ? c.uw_lo_d : c.uw_hi_d; }
-        if (c.wall_y && (nyg < 0 || nyg >= g.ny)) { gy_ = true; qy = uy_; uwx = nyg < 0 ? c.uw_lo_d : c.uw_hi_d; }
-        double vx = (qx == ux_ && qy == uy_) ? n.ux : (double)s.u[0][qy][qx];
-        double vy = (qx == ux_ && qy == uy_) ? n.uy : (double)s.u[1][qy][qx];
-        if (gx_) { vx = -vx; vy = 2.0 * uwy - vy; }
-        if (gy_) { vx = 2.0 * uwx - vx; vy = -vy; }
-        const double ph = s.phi[py + cy(i)][px + cx(i)];
-        dq += wtd(i) * ((double)cx(i) * (ph * vx) + (double)cy(i) * (ph * vy));
+    for (int i = 1; i < 9; ++i) {
+      int qy = uy_ + cy(i), qx = ux_ + cx(i);
+      const int nxg = x + cx(i), nyg = y + cy(i);
+      const bool gx_ = c.wall_x && (nxg < 0 || nxg >= g.nx);
+      const bool gy_ = c.wall_y && (nyg < 0 || nyg >= g.ny);
+      if (gx_) qx = ux_;
+      if (gy_) qy = uy_;
+      float vx = s.q[0][qy][qx], vy = s.q[1][qy][qx];
+      if (gx_ || gy_) {
+        const float phm = (float)s.phi[qy + 2][qx + 2];
+        if (gx_) { vx = -vx; vy = 2.f * (nxg < 0 ? c.uw_lo : c.uw_hi) * phm - vy; }
+        if (gy_) { vx = 2.f * (nyg < 0 ? c.uw_lo : c.uw_hi) * phm - vx; vy = -vy; }
       }
-      dq *= 3.0;
-      const long long o = (long long)y * g.pitch + x;
-      const double qx = phid * n.ux, qy = phid * n.uy;
-      const double dtx = qx - (double)a.J[o], dty = qy - (double)a.J[g.ps + o];   // explicit-Euler d_t(phi u) (A4)
-      a.J[o] = (float)qx;
-      a.J[g.ps + o] = (float)qy;
-      a.pout[o] = n.Pn;
-
-      if (!(isfinite(n.ux) && isfinite(n.uy) && isfinite(phid))) atomicOr(a.status, 1);
-
-      const double tau_f = 0.5 + 3.0 * mu_of(phid, c) / n.rho;   // A6
-      const double omf = 1.0 / tau_f, cff = 1.0 - 0.5 * omf;
-      const double omh = c.inv_tau_h_d, cfh = 1.0 - 0.5 * omh;
-      const double usq = n.ux * n.ux + n.uy * n.uy;
-      const double cs2rho = n.rho / 3.0;
-      const double dPn = n.P - (double)n.Pn;
-
-      // pulled h_i (i >= 1); h_0 - phi = -sum_{i>=1} h_i
-      float h[9];
+      dqf += wt(i) * ((float)cx(i) * vx + (float)cy(i) * vy);
+    }
+    const double dq = 3.0 * (double)dqf;
+    {
       const int wx = c.wall_x, wy = c.wall_y;
       h[1] = pull<1>(a.hin, x, y, g, wx, wy);
       h[2] = pull<2>(a.hin, x, y, g, wx, wy);
@@ -424,55 +413,73 @@ __global__ __launch_bounds__(kThreads) void k_fused(StepArgs a, MomentArgs m) {
       h[6] = pull<6>(a.hin, x, y, g, wx, wy);
       h[7] = pull<7>(a.hin, x, y, g, wx, wy);
       h[8] = pull<8>(a.hin, x, y, g, wx, wy);
-      const double etamu = c.eta_d * n.mu;
-      const double hsrc = c.a_h_d * dq;
-      double d0sum = 0.0;   // sum of the stored h_i^+ (i >= 1)
+      const int oj = y * g.pitch + x;
+      j0 = a.J[(unsigned)oj];
+      j1 = a.J[(unsigned)(g.psi + oj)];
+    }
+    const int o = y * g.pitch + x;
+    const double qx = phid * n.ux, qy = phid * n.uy;
+    const double dtx = qx - (double)j0, dty = qy - (double)j1;   // explicit-Euler d_t(phi u) (A4)
+    a.J[(unsigned)o] = (float)qx;
+    a.J[(unsigned)(g.psi + o)] = (float)qy;
+    a.pout[(unsigned)o] = n.Pn;
+
+    if (!(isfinite(n.ux) && isfinite(n.uy) && isfinite(phid))) atomicOr(a.status, 1);
+
+    const double tau_f = 0.5 + 3.0 * mu_of(phid, c) * rcp64(n.rho);   // A6
+    const double omf = rcp64(tau_f), cff = 1.0 - 0.5 * omf;
+    const double omh = c.inv_tau_h_d, cfh = 1.0 - 0.5 * omh;
+    const double usq = n.ux * n.ux + n.uy * n.uy;
+    const double cs2rho = n.rho * (1.0 / 3.0);
+    const double dPn = n.P - (double)n.Pn;
+    const double etamu = c.eta_d * (double)n.mu;
+    const double hsrc = c.a_h_d * dq;
+    double d0sum = 0.0;   // sum of the stored h_i^+ (i >= 1)
 
 #pragma unroll
-      for (int i = 1; i < 9; ++i) {
-        const double cu = (double)cx(i) * n.ux + (double)cy(i) * n.uy;
-        const double si = 3.0 * cu + 4.5 * cu * cu - 1.5 * usq;      // s_i(u), Eq. (33)
-        const double heq = wtd(i) * etamu + wtd(i) * phid * 3.0 * cu;   // Eq. (32)
-        const double Hi = wtd(i) * hsrc + wtd(i) * 3.0 * ((double)cx(i) * dtx + (double)cy(i) * dty);   // Eq. (36)
-        double hp = (double)h[i] - ((double)h[i] - heq) * omh + cfh * Hi;   // Eq. (30)
-        // Eq. (43): a population about to cross a wall is stored in its own
-        // slot with the moving-wall term; the next pull reads it as opp(i).
+    for (int i = 1; i < 9; ++i) {
+      const double cu = (double)cx(i) * n.ux + (double)cy(i) * n.uy;
+      const double heq = wtd(i) * etamu + wtd(i) * phid * 3.0 * cu;   // Eq. (32)
+      const double Hi = wtd(i) * hsrc + wtd(i) * 3.0 * ((double)cx(i) * dtx + (double)cy(i) * dty);   // Eq. (36)
+      double hp = (double)h[i] - ((double)h[i] - heq) * omh + cfh * Hi;   // Eq. (30)
+      // Eq. (43): a population about to cross a wall is stored in its own
+      // slot with the moving-wall term; the next pull reads it as opp(i).
+      const int tx = x + cx(i), tyy = y + cy(i);
+      double cuw = 0.0;
+      bool hit = false;
+      if (c.wall_x && (tx < 0 || tx >= g.nx)) { hit = true; cuw = (double)cy(i) * (tx < 0 ? c.uw_lo_d : c.uw_hi_d); }
+      if (c.wall_y && (tyy < 0 || tyy >= g.ny)) { hit = true; cuw = (double)cx(i) * (tyy < 0 ? c.uw_lo_d : c.uw_hi_d); }
+      if (hit) hp -= 6.0 * wtd(i) * phid * cuw;
+      const float hs = (float)hp;
+      d0sum += (double)hs;
+      a.hout[(unsigned)(i * g.psi + o)] = hs;
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // slot 0 holds d0 = h_0^+ - phi.  The collision conserves sum_i h_i = phi
+    // (Eqs. 32 and 36), so d0 = -sum_{i>=1} h_i^+ exactly; forming it from
+    // the stored values makes the update of phi conservative.
+    a.hout[(unsigned)o] = (float)(-d0sum);
+
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const double cu = (double)cx(i) * n.ux + (double)cy(i) * n.uy;
+      const double si = 3.0 * cu + 4.5 * cu * cu - 1.5 * usq;      // s_i(u), Eq. (33)
+      const double feq = wtd(i) * (dPn + cs2rho * si);              // f_i^eq - w_i Pn, Eq. (31)
+      const double gam = wtd(i) * (1.0 + si);                       // Gamma_i (A1)
+      const double Fi = ((double)cx(i) - n.ux) * (gam * (double)n.fx + wtd(i) * si * (1.0 / 3.0) * (double)n.grx) +
+                        ((double)cy(i) - n.uy) * (gam * (double)n.fy + wtd(i) * si * (1.0 / 3.0) * (double)n.gry);   // Eq. (35)
+      const double fi = (double)n.f[i];
+      double fp = fi - (fi - feq) * omf + cff * Fi;                 // Eq. (29), minus w_i Pn
+      if (i != 0) {
         const int tx = x + cx(i), tyy = y + cy(i);
         double cuw = 0.0;
         bool hit = false;
         if (c.wall_x && (tx < 0 || tx >= g.nx)) { hit = true; cuw = (double)cy(i) * (tx < 0 ? c.uw_lo_d : c.uw_hi_d); }
         if (c.wall_y && (tyy < 0 || tyy >= g.ny)) { hit = true; cuw = (double)cx(i) * (tyy < 0 ? c.uw_lo_d : c.uw_hi_d); }
-        if (hit) hp -= 6.0 * wtd(i) * phid * cuw;
-        const float hs = (float)hp;
-        d0sum += (double)hs;
-        a.hout[(long long)i * g.ps + o] = hs;
-        (void)si;
+        if (hit) fp -= 2.0 * wtd(i) * n.rho * cuw;
       }
-      // slot 0 holds d0 = h_0^+ - phi.  The collision conserves sum_i h_i = phi
-      // (Eqs. 32 and 36), so d0 = -sum_{i>=1} h_i^+ exactly; forming it from
-      // the stored values makes the update of phi conservative.
-      a.hout[o] = (float)(-d0sum);
-
-#pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        const double cu = (double)cx(i) * n.ux + (double)cy(i) * n.uy;
-        const double si = 3.0 * cu + 4.5 * cu * cu - 1.5 * usq;      // s_i(u), Eq. (33)
-        const double feq = wtd(i) * (dPn + cs2rho * si);              // f_i^eq - w_i Pn, Eq. (31)
-        const double gam = wtd(i) * (1.0 + si);                       // Gamma_i (A1)
-        const double Fi = ((double)cx(i) - n.ux) * (gam * n.fx + wtd(i) * si * (1.0 / 3.0) * n.grx) +
-                          ((double)cy(i) - n.uy) * (gam * n.fy + wtd(i) * si * (1.0 / 3.0) * n.gry);   // Eq. (35)
-        const double fi = (double)n.f[i];
-        double fp = fi - (fi - feq) * omf + cff * Fi;                 // Eq. (29), minus w_i Pn
-        if (i != 0) {
-          const int tx = x + cx(i), tyy = y + cy(i);
-          double cuw = 0.0;
-          bool hit = false;
-          if (c.wall_x && (tx < 0 || tx >= g.nx)) { hit = true; cuw = (double)cy(i) * (tx < 0 ? c.uw_lo_d : c.uw_hi_d); }
-          if (c.wall_y && (tyy < 0 || tyy >= g.ny)) { hit = true; cuw = (double)cx(i) * (tyy < 0 ? c.uw_lo_d : c.uw_hi_d); }
-          if (hit) fp -= 2.0 * wtd(i) * n.rho * cuw;
-        }
-        a.fout[(long long)i * g.ps + o] = (float)fp;
-      }
+      a.fout[(unsigned)(i * g.psi + o)] = (float)fp;
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
@@ -483,8 +490,8 @@ __global__ __launch_bounds__(256) void k_phi(const float* __restrict__ h, double
   const int x = blockIdx.x * 64 + (threadIdx.x & 63);
   const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (x >= g.nx || y >= g.ny) return;
-  const long long o = (long long)y * g.pitch + x;
-  double s = (double)h[o];
+  const int o = y * g.pitch + x;
+  double s = (double)h[(unsigned)o];
   s += (double)pull<1>(h, x, y, g, wx, wy);
   s += (double)pull<2>(h, x, y, g, wx, wy);
   s += (double)pull<3>(h, x, y, g, wx, wy);
@@ -493,7 +500,7 @@ __global__ __launch_bounds__(256) void k_phi(const float* __restrict__ h, double
   s += (double)pull<6>(h, x, y, g, wx, wy);
   s += (double)pull<7>(h, x, y, g, wx, wy);
   s += (double)pull<8>(h, x, y, g, wx, wy);
-  phi[o] += s;
+  phi[(unsigned)o] += s;
 }
 
 // Initial state, pass 1: node-local f^eq(P = 0, rho(phi0), u0) and
@@ -595,8 +602,8 @@ __global__ void k_fill_int(int* p, int v, int n) {
 template <int FORM>
 hipError_t launch_fused_t(const StepArgs& a, const MomentArgs& m, bool moments, hipStream_t st) {
   dim3 grid((a.g.nx + kTX - 1) / kTX, (a.g.ny + kTY - 1) / kTY);
-  if (moments) hipLaunchKernelGGL((k_fused<FORM, true>), grid, dim3(kThreads), 0, st, a, m);
-  else hipLaunchKernelGGL((k_fused<FORM, false>), grid, dim3(kThreads), 0, st, a, m);
+  if (moments) hipLaunchKernelGGL((k_fused<FORM, true>), grid, dim3(kFusedThreads), 0, st, a, m);
+  else hipLaunchKernelGGL((k_fused<FORM, false>), grid, dim3(kFusedThreads), 0, st, a, m);
   return hipGetLastError();
 }
 
