@@ -24,6 +24,7 @@ constexpr int UW = kTX + 2, UH = kTY + 2;   // velocity ring (halo 1)
 constexpr int NRING = 2 * UW + 2 * kTY;     // positions of the velocity ring
 constexpr float CS2 = 1.0f / 3.0f;
 constexpr int kFusedThreads = kTX * kTY;   // one node per thread
+constexpr int kXcds = 8;                    // accelerator complex dies of the MI355X
 
 __device__ __forceinline__ int wrap_or_reflect(int c, int n, int wall) {
   if (wall) {
@@ -33,6 +34,21 @@ __device__ __forceinline__ int wrap_or_reflect(int c, int n, int wall) {
   }
   c %= n;
   return c < 0 ? c + n : c;
+}
+
+// Tile-halo coordinate c in [-3, tile end + 3]: one periodic wrap or one
+// mirror about the half-way wall.  Every position an active node reads lies
+// within [-3, n + 3] (n >= 8), where one step is exact; the clamp keeps the
+// positions of a ragged tile that no active node reads inside the array.
+template <bool WALL>
+__device__ __forceinline__ int halo_coord(int c, int n) {
+  if constexpr (WALL) {
+    c = c < 0 ? -1 - c : (c >= n ? 2 * n - 1 - c : c);
+    return c < 0 ? 0 : c;
+  } else {
+    c = c < 0 ? c + n : (c >= n ? c - n : c);
+    return c < n ? c : n - 1;
+  }
 }
 
 // Source of the pulled population i for node (x, y) inside the domain: the
@@ -80,6 +96,7 @@ __device__ __forceinline__ double mu_of(double phi, const Phys& c) { return c.mu
 
 struct Lds {
   double phi[PH][PW];
+  double gl[3][BH][BW];   // grad phi (x, y) and lap phi on the 2-ring
   double b[3][BH][BW];
   float q[2][UH][UW];   // phi u on the tile and its 1-node ring
 };
@@ -124,14 +141,18 @@ __device__ __forceinline__ void grad_b(const double (*f)[BW], int by, int bx, do
 // differences are small against their values).
 template <int FORM>
 __device__ __forceinline__ void stage_b(Lds& s, int tid, const Phys& c) {
-  if constexpr (FORM == 3 || FORM == 4) return;   // CPF-2, PF-1: pointwise at radius 1
   const double kappa = c.kappa_d;
   for (int k = tid; k < BH * BW; k += kFusedThreads) {
     const int by = k / BW, bx = k - by * BW;
     const int py = by + 1, px = bx + 1;
     double gx, gy, lap;
     grad_lap_phi(s, py, px, gx, gy, lap);
-    if constexpr (FORM == 0) {          // STF-1: T = -kappa G (x) G, F = div T
+    s.gl[0][by][bx] = gx;
+    s.gl[1][by][bx] = gy;
+    s.gl[2][by][bx] = lap;
+    if constexpr (FORM == 3 || FORM == 4) {
+      // CPF-2, PF-1: pointwise in G and lap phi
+    } else if constexpr (FORM == 0) {          // STF-1: T = -kappa G (x) G, F = div T
       s.b[0][by][bx] = -kappa * gx * gx;
       s.b[1][by][bx] = -kappa * gx * gy;
       s.b[2][by][bx] = -kappa * gy * gy;
@@ -177,14 +198,12 @@ __device__ __forceinline__ void force_sf(const Lds& s, int uy_, int ux_, const P
     fx = -phi * gx;
     fy = -phi * gy;
   } else if constexpr (FORM == 3) {         // CPF-2: mu grad(phi)
-    double gx, gy, lap;
-    grad_lap_phi(s, py, px, gx, gy, lap);
+    const double gx = s.gl[0][by][bx], gy = s.gl[1][by][bx], lap = s.gl[2][by][bx];
     const double mu = chem_pot(s.phi[py][px], lap, c);
     fx = mu * gx;
     fy = mu * gy;
   } else if constexpr (FORM == 4) {         // PF-1: -kappa grad(phi) lap(phi)
-    double gx, gy, lap;
-    grad_lap_phi(s, py, px, gx, gy, lap);
+    const double gx = s.gl[0][by][bx], gy = s.gl[1][by][bx], lap = s.gl[2][by][bx];
     fx = -kappa * gx * lap;
     fy = -kappa * gy * lap;
   } else if constexpr (FORM == 5) {         // PF-2: kappa phi grad(lap phi)
@@ -203,8 +222,7 @@ __device__ __forceinline__ void force_sf(const Lds& s, int uy_, int ux_, const P
       dn += wtd(i) * ((double)cx(i) * dx + (double)cy(i) * dy);
     }
     dn *= 3.0;
-    double gx, gy, lap;
-    grad_lap_phi(s, py, px, gx, gy, lap);
+    const double gx = s.gl[0][by][bx], gy = s.gl[1][by][bx];
     if constexpr (FORM == 6) {              // CSF-1: -kappa |G|^2 n div n
       const double k = -kappa * (gx * gx + gy * gy) * dn;
       fx = k * nxc;
@@ -229,8 +247,9 @@ struct NodeState {
 
 // Pull the stored flow populations and the pressures of their source nodes
 // for node (x, y) inside the domain (Eqs. 29 and 43, pull form).
+template <bool WX, bool WY>
 __device__ __forceinline__ void load_fp(const StepArgs& a, int x, int y, float* ft, float* ps) {
-  const int wx = a.c.wall_x, wy = a.c.wall_y;
+  constexpr int wx = WX, wy = WY;
 #define PULL_FP(I)                                               \
   {                                                              \
     int sl_;                                                     \
@@ -268,8 +287,7 @@ __device__ __forceinline__ void velocity_from(const Lds& s, const StepArgs& a, i
   ns.ux = ux;
   ns.uy = uy;
   if constexpr (FULL) {
-    double gx, gy, lap;
-    grad_lap_phi(s, uy_ + 2, ux_ + 2, gx, gy, lap);
+    const double gx = s.gl[0][uy_ + 1][ux_ + 1], gy = s.gl[1][uy_ + 1][ux_ + 1], lap = s.gl[2][uy_ + 1][ux_ + 1];
     const double grx = a.c.drho_half_d * gx, gry = a.c.drho_half_d * gy;   // grad rho = (rho1 - rho2)/2 grad phi
     ns.fx = (float)fx;
     ns.fy = (float)fy;
@@ -301,39 +319,58 @@ __device__ __forceinline__ void ring_pos(int k, int& uy_, int& ux_) {
 
 // Global position of ring position, wrapped on periodic axes; returns false
 // when it lies beyond a wall (its velocity is then never read directly).
+template <bool WX, bool WY>
 __device__ __forceinline__ bool ring_global(int uy_, int ux_, int x0, int y0, const StepArgs& a, int& x, int& y) {
   x = x0 + ux_ - 1;
   y = y0 + uy_ - 1;
-  if (a.c.wall_x) { if (x < 0 || x >= a.g.nx) return false; }
+  if constexpr (WX) { if (x < 0 || x >= a.g.nx) return false; }
   else { x %= a.g.nx; if (x < 0) x += a.g.nx; }
-  if (a.c.wall_y) { if (y < 0 || y >= a.g.ny) return false; }
+  if constexpr (WY) { if (y < 0 || y >= a.g.ny) return false; }
   else { y %= a.g.ny; if (y < 0) y += a.g.ny; }
   return true;
 }
 
-template <int FORM, bool MOMENTS>
-__global__ __launch_bounds__(kFusedThreads) void k_fused(StepArgs a, MomentArgs m) {
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Tile t is given to workgroup (t % per) * 8 + t / per, so every XCD
+// sweeps one contiguous band of tiles (row-major) and the halos it shares
+// with the previous tile and tile row are L2 hits.  Returns false for the
+// padding workgroups past the last tile.
+__device__ __forceinline__ bool xcd_tile(int ntx, int nty, int& tx, int& ty) {
+  const int n = ntx * nty, per = (n + kXcds - 1) / kXcds;
+  const int wg = blockIdx.x;
+  const int t = (wg % kXcds) * per + wg / kXcds;
+  if (t >= n) return false;
+  ty = t / ntx;
+  tx = t - ty * ntx;
+  return true;
+}
+
+template <int FORM, bool MOMENTS, int BC>
+__global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_fused(StepArgs a, MomentArgs m) {
+  constexpr bool WX = (BC & 1) != 0, WY = (BC & 2) != 0;   // walled axes (compile time)
   __shared__ Lds s;
   const int tid = threadIdx.x;
-  const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY;
+  int tile_x, tile_y;
+  if (!xcd_tile((a.g.nx + kTX - 1) / kTX, (a.g.ny + kTY - 1) / kTY, tile_x, tile_y)) return;
+  const int x0 = tile_x * kTX, y0 = tile_y * kTY;
   const int lx = tid & (kTX - 1), ty = tid / kTX;   // one node per thread
   const Grid& g = a.g;
   const Phys& c = a.c;
   const int uy_ = ty + 1, ux_ = lx + 1;             // velocity-ring coordinates of this node
   int x, y;
-  const bool valid = ring_global(uy_, ux_, x0, y0, a, x, y);
+  const bool valid = ring_global<WX, WY>(uy_, ux_, x0, y0, a, x, y);
   const bool act = (x0 + lx < g.nx) && (y0 + ty < g.ny);
 
   // This node's HBM reads are issued first so they complete while the LDS
   // stencil stages run.
   float ft[9], ps[9], h[9];
   float j0 = 0.f, j1 = 0.f;
-  if (valid) load_fp(a, x, y, ft, ps);
+  if (valid) load_fp<WX, WY>(a, x, y, ft, ps);
   // Stage A: phi tile with a 3-node halo (periodic wrap / even reflection at walls, Sec. IV)
   for (int k = tid; k < PH * PW; k += kFusedThreads) {
     const int py = k / PW, px = k - py * PW;
-    const int gx = wrap_or_reflect(x0 + px - 3, g.nx, c.wall_x);
-    const int gy = wrap_or_reflect(y0 + py - 3, g.ny, c.wall_y);
+    const int gx = halo_coord<WX>(x0 + px - 3, g.nx);
+    const int gy = halo_coord<WY>(y0 + py - 3, g.ny);
     s.phi[py][px] = a.phi[(unsigned)(gy * g.pitch + gx)];
   }
   __syncthreads();
@@ -346,9 +383,9 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(StepArgs a, MomentArgs 
     if (tid < NRING) {
       int ruy, rux, rx, ry;
       ring_pos(tid, ruy, rux);
-      if (ring_global(ruy, rux, x0, y0, a, rx, ry)) {
+      if (ring_global<WX, WY>(ruy, rux, x0, y0, a, rx, ry)) {
         float rft[9], rps[9];
-        load_fp(a, rx, ry, rft, rps);
+        load_fp<WX, WY>(a, rx, ry, rft, rps);
         NodeState rs;
         velocity_from<FORM, false>(s, a, ruy, rux, rft, rps, rs);
         const double ph = s.phi[ruy + 2][rux + 2];
@@ -390,8 +427,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(StepArgs a, MomentArgs 
     for (int i = 1; i < 9; ++i) {
       int qy = uy_ + cy(i), qx = ux_ + cx(i);
       const int nxg = x + cx(i), nyg = y + cy(i);
-      const bool gx_ = c.wall_x && (nxg < 0 || nxg >= g.nx);
-      const bool gy_ = c.wall_y && (nyg < 0 || nyg >= g.ny);
+      const bool gx_ = WX && (nxg < 0 || nxg >= g.nx);
+      const bool gy_ = WY && (nyg < 0 || nyg >= g.ny);
       if (gx_) qx = ux_;
       if (gy_) qy = uy_;
       float vx = s.q[0][qy][qx], vy = s.q[1][qy][qx];
@@ -404,7 +441,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(StepArgs a, MomentArgs 
     }
     const double dq = 3.0 * (double)dqf;
     {
-      const int wx = c.wall_x, wy = c.wall_y;
+      constexpr int wx = WX, wy = WY;
       h[1] = pull<1>(a.hin, x, y, g, wx, wy);
       h[2] = pull<2>(a.hin, x, y, g, wx, wy);
       h[3] = pull<3>(a.hin, x, y, g, wx, wy);
@@ -430,56 +467,65 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(StepArgs a, MomentArgs 
     const double omf = rcp64(tau_f), cff = 1.0 - 0.5 * omf;
     const double omh = c.inv_tau_h_d, cfh = 1.0 - 0.5 * omh;
     const double usq = n.ux * n.ux + n.uy * n.uy;
-    const double cs2rho = n.rho * (1.0 / 3.0);
-    const double dPn = n.P - (double)n.Pn;
-    const double etamu = c.eta_d * (double)n.mu;
-    const double hsrc = c.a_h_d * dq;
-    double d0sum = 0.0;   // sum of the stored h_i^+ (i >= 1)
 
+    // Order-parameter collision, Eq. (30) with h^eq of Eq. (32) and H_i of
+    // Eq. (36), factored per node:  h_i^+ = (1 - 1/tau_h) h_i + w_i [G0 + 3 c_i.V]
+    // with G0 = eta mu / tau_h + (1 - 1/(2 tau_h)) A_H div(phi u) and
+    // V = phi u / tau_h + (1 - 1/(2 tau_h)) d_t(phi u).
+    const double G0 = omh * c.eta_d * (double)n.mu + cfh * (c.a_h_d * dq);
+    const double Vx = omh * qx + cfh * dtx, Vy = omh * qy + cfh * dty;
+    const double keep_h = 1.0 - omh;
+    double d0sum = 0.0;   // sum of the stored h_i^+ (i >= 1)
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
-      const double cu = (double)cx(i) * n.ux + (double)cy(i) * n.uy;
-      const double heq = wtd(i) * etamu + wtd(i) * phid * 3.0 * cu;   // Eq. (32)
-      const double Hi = wtd(i) * hsrc + wtd(i) * 3.0 * ((double)cx(i) * dtx + (double)cy(i) * dty);   // Eq. (36)
-      double hp = (double)h[i] - ((double)h[i] - heq) * omh + cfh * Hi;   // Eq. (30)
+      const double cV = (cx(i) != 0 ? cx(i) * Vx : 0.0) + (cy(i) != 0 ? cy(i) * Vy : 0.0);
+      double hp = keep_h * (double)h[i] + wtd(i) * (G0 + 3.0 * cV);
       // Eq. (43): a population about to cross a wall is stored in its own
       // slot with the moving-wall term; the next pull reads it as opp(i).
       const int tx = x + cx(i), tyy = y + cy(i);
       double cuw = 0.0;
       bool hit = false;
-      if (c.wall_x && (tx < 0 || tx >= g.nx)) { hit = true; cuw = (double)cy(i) * (tx < 0 ? c.uw_lo_d : c.uw_hi_d); }
-      if (c.wall_y && (tyy < 0 || tyy >= g.ny)) { hit = true; cuw = (double)cx(i) * (tyy < 0 ? c.uw_lo_d : c.uw_hi_d); }
+      if (WX && (tx < 0 || tx >= g.nx)) { hit = true; cuw = (double)cy(i) * (tx < 0 ? c.uw_lo_d : c.uw_hi_d); }
+      if (WY && (tyy < 0 || tyy >= g.ny)) { hit = true; cuw = (double)cx(i) * (tyy < 0 ? c.uw_lo_d : c.uw_hi_d); }
       if (hit) hp -= 6.0 * wtd(i) * phid * cuw;
       const float hs = (float)hp;
       d0sum += (double)hs;
       a.hout[(unsigned)(i * g.psi + o)] = hs;
-      __builtin_amdgcn_sched_barrier(0);
     }
     // slot 0 holds d0 = h_0^+ - phi.  The collision conserves sum_i h_i = phi
     // (Eqs. 32 and 36), so d0 = -sum_{i>=1} h_i^+ exactly; forming it from
     // the stored values makes the update of phi conservative.
     a.hout[(unsigned)o] = (float)(-d0sum);
 
+    // Flow collision, Eq. (29) with f^eq of Eq. (31) and F_i of Eq. (35)
+    // (reading A1), factored per node.  With s_i = 3 c.u + 4.5 (c.u)^2 - 1.5 u^2,
+    // F = F_sf + F_g and grad rho:
+    //   f_i^+ - w_i Pn = (1 - 1/tau_f) (f_i - w_i Pn)
+    //        + w_i [K0 + k c.F + s_i (K1 + k c.F + k c.grad(rho)/3)],
+    //   k = 1 - 1/(2 tau_f), K0 = (P - Pn)/tau_f - k u.F,
+    //   K1 = rho/(3 tau_f) - k u.F - k u.grad(rho)/3.
+    const double fx = (double)n.fx, fy = (double)n.fy, grx = (double)n.grx, gry = (double)n.gry;
+    const double uF = n.ux * fx + n.uy * fy, uG = n.ux * grx + n.uy * gry;
+    const double K0 = omf * (n.P - (double)n.Pn) - cff * uF;
+    const double K1 = omf * n.rho * (1.0 / 3.0) - cff * uF - cff * uG * (1.0 / 3.0);
+    const double kFx = cff * fx, kFy = cff * fy, kGx = cff * grx * (1.0 / 3.0), kGy = cff * gry * (1.0 / 3.0);
+    const double keep_f = 1.0 - omf, m15usq = -1.5 * usq;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      const double cu = (double)cx(i) * n.ux + (double)cy(i) * n.uy;
-      const double si = 3.0 * cu + 4.5 * cu * cu - 1.5 * usq;      // s_i(u), Eq. (33)
-      const double feq = wtd(i) * (dPn + cs2rho * si);              // f_i^eq - w_i Pn, Eq. (31)
-      const double gam = wtd(i) * (1.0 + si);                       // Gamma_i (A1)
-      const double Fi = ((double)cx(i) - n.ux) * (gam * (double)n.fx + wtd(i) * si * (1.0 / 3.0) * (double)n.grx) +
-                        ((double)cy(i) - n.uy) * (gam * (double)n.fy + wtd(i) * si * (1.0 / 3.0) * (double)n.gry);   // Eq. (35)
-      const double fi = (double)n.f[i];
-      double fp = fi - (fi - feq) * omf + cff * Fi;                 // Eq. (29), minus w_i Pn
+      const double cu = (cx(i) != 0 ? cx(i) * n.ux : 0.0) + (cy(i) != 0 ? cy(i) * n.uy : 0.0);
+      const double si = fma(fma(4.5, cu, 3.0), cu, m15usq);        // s_i(u), Eq. (33)
+      const double cF = (cx(i) != 0 ? cx(i) * kFx : 0.0) + (cy(i) != 0 ? cy(i) * kFy : 0.0);
+      const double cG = (cx(i) != 0 ? cx(i) * kGx : 0.0) + (cy(i) != 0 ? cy(i) * kGy : 0.0);
+      double fp = keep_f * (double)n.f[i] + wtd(i) * (K0 + cF + si * (K1 + cF + cG));
       if (i != 0) {
         const int tx = x + cx(i), tyy = y + cy(i);
         double cuw = 0.0;
         bool hit = false;
-        if (c.wall_x && (tx < 0 || tx >= g.nx)) { hit = true; cuw = (double)cy(i) * (tx < 0 ? c.uw_lo_d : c.uw_hi_d); }
-        if (c.wall_y && (tyy < 0 || tyy >= g.ny)) { hit = true; cuw = (double)cx(i) * (tyy < 0 ? c.uw_lo_d : c.uw_hi_d); }
+        if (WX && (tx < 0 || tx >= g.nx)) { hit = true; cuw = (double)cy(i) * (tx < 0 ? c.uw_lo_d : c.uw_hi_d); }
+        if (WY && (tyy < 0 || tyy >= g.ny)) { hit = true; cuw = (double)cx(i) * (tyy < 0 ? c.uw_lo_d : c.uw_hi_d); }
         if (hit) fp -= 2.0 * wtd(i) * n.rho * cuw;
       }
       a.fout[(unsigned)(i * g.psi + o)] = (float)fp;
-      __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
@@ -487,8 +533,10 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(StepArgs a, MomentArgs 
 // phi^{n+1}(x) = phi^n(x) + d0(x) + sum_{i>=1} h_i^+(x - c_i)   (Eq. 37, phi = sum h_i)
 __global__ __launch_bounds__(256) void k_phi(const float* __restrict__ h, double* __restrict__ phi, Grid g, int wx,
                                              int wy) {
-  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  int bx, by;
+  if (!xcd_tile((g.nx + 63) / 64, (g.ny + 3) / 4, bx, by)) return;
+  const int x = bx * 64 + (threadIdx.x & 63);
+  const int y = by * 4 + (threadIdx.x >> 6);
   if (x >= g.nx || y >= g.ny) return;
   const int o = y * g.pitch + x;
   double s = (double)h[(unsigned)o];
@@ -599,24 +647,35 @@ __global__ void k_fill_int(int* p, int v, int n) {
   if (k < n) p[k] = v;
 }
 
-template <int FORM>
+template <int FORM, int BC>
 hipError_t launch_fused_t(const StepArgs& a, const MomentArgs& m, bool moments, hipStream_t st) {
-  dim3 grid((a.g.nx + kTX - 1) / kTX, (a.g.ny + kTY - 1) / kTY);
-  if (moments) hipLaunchKernelGGL((k_fused<FORM, true>), grid, dim3(kFusedThreads), 0, st, a, m);
-  else hipLaunchKernelGGL((k_fused<FORM, false>), grid, dim3(kFusedThreads), 0, st, a, m);
+  const int ntiles = ((a.g.nx + kTX - 1) / kTX) * ((a.g.ny + kTY - 1) / kTY);
+  dim3 grid((ntiles + kXcds - 1) / kXcds * kXcds);
+  if (moments) hipLaunchKernelGGL((k_fused<FORM, true, BC>), grid, dim3(kFusedThreads), 0, st, a, m);
+  else hipLaunchKernelGGL((k_fused<FORM, false, BC>), grid, dim3(kFusedThreads), 0, st, a, m);
   return hipGetLastError();
+}
+
+template <int FORM>
+hipError_t launch_form(const StepArgs& a, const MomentArgs& m, bool moments, hipStream_t st) {
+  switch (a.c.wall_x | (a.c.wall_y << 1)) {
+    case 0: return launch_fused_t<FORM, 0>(a, m, moments, st);
+    case 1: return launch_fused_t<FORM, 1>(a, m, moments, st);
+    case 2: return launch_fused_t<FORM, 2>(a, m, moments, st);
+    default: return launch_fused_t<FORM, 3>(a, m, moments, st);
+  }
 }
 
 hipError_t dispatch(int form, const StepArgs& a, const MomentArgs& m, bool moments, hipStream_t st) {
   switch (form) {
-    case 0: return launch_fused_t<0>(a, m, moments, st);
-    case 1: return launch_fused_t<1>(a, m, moments, st);
-    case 2: return launch_fused_t<2>(a, m, moments, st);
-    case 3: return launch_fused_t<3>(a, m, moments, st);
-    case 4: return launch_fused_t<4>(a, m, moments, st);
-    case 5: return launch_fused_t<5>(a, m, moments, st);
-    case 6: return launch_fused_t<6>(a, m, moments, st);
-    case 7: return launch_fused_t<7>(a, m, moments, st);
+    case 0: return launch_form<0>(a, m, moments, st);
+    case 1: return launch_form<1>(a, m, moments, st);
+    case 2: return launch_form<2>(a, m, moments, st);
+    case 3: return launch_form<3>(a, m, moments, st);
+    case 4: return launch_form<4>(a, m, moments, st);
+    case 5: return launch_form<5>(a, m, moments, st);
+    case 6: return launch_form<6>(a, m, moments, st);
+    case 7: return launch_form<7>(a, m, moments, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -630,7 +689,8 @@ hipError_t launch_moments(int form, const StepArgs& a, const MomentArgs& m, hipS
 }
 
 hipError_t launch_phi(const float* h, double* phi, const Grid& g, int wall_x, int wall_y, hipStream_t s) {
-  dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4);
+  const int nb = ((g.nx + 63) / 64) * ((g.ny + 3) / 4);
+  dim3 grid((nb + kXcds - 1) / kXcds * kXcds);
   hipLaunchKernelGGL(k_phi, grid, dim3(256), 0, s, h, phi, g, wall_x, wall_y);
   return hipGetLastError();
 }
