@@ -79,6 +79,51 @@ def cpu_baseline(budget_s=20.0):
             "sample": f"{n} time steps of the 2048x2048 droplet (forms round-robin, FP64 torch CPU) after 1 warm-up step, {el:.1f} s"}
 
 
+def bench_batched(steps, loop_steps):
+    """512 independent two-droplet instances (sides 32..512, random force form,
+    density ratio and sigma; numpy default_rng(14729)), one persistent
+    graph-replayed batched step vs looping the single-lattice lbm_step."""
+    import numpy as np
+    import torch
+
+    import paper_2012_14729_amd as P
+    import workloads as WL
+
+    insts = WL.batch_instances(512, seed=14729)
+    params = [p.as_dict() for p, _, _ in insts]
+    forms = [f for _, f, _ in insts]
+    phis = [np.asarray(x, np.float32) for _, _, x in insts]
+    cells = sum(p["nx"] * p["ny"] for p in params)
+    print(f"[bench] batched: 512 instances, {cells} nodes", file=sys.stderr, flush=True)
+    b = P.Batch(params, forms, phis)
+    b.step(16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    unstable = sum(b.status())
+    del b
+    torch.cuda.empty_cache()
+    sims = [P.Simulation(pp, x) for pp, x in zip(params, phis)]
+    for s, f in zip(sims, forms):
+        s.step(2, f)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(loop_steps):
+        for s, f in zip(sims, forms):
+            s.step(1, f)
+    torch.cuda.synchronize()
+    el_loop = time.perf_counter() - t1
+    del sims
+    torch.cuda.empty_cache()
+    batched = cells * steps / el / 1e6
+    loop = cells * loop_steps / el_loop / 1e6
+    return {"MLUPS": round(batched, 1), "instances": 512, "nodes": cells, "steps": steps,
+            "looping_plain_lbm_step_MLUPS": round(loop, 1), "loop_steps": loop_steps,
+            "speedup_vs_loop": round(batched / loop, 2), "unstable_instances": unstable}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +131,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=80)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--size", type=int, default=2048)
+    ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (multi-GPU sharding is a "
@@ -171,6 +218,12 @@ def main():
         "batched": None,
         "adjoint": None,
     }
+    value_per_form = value
+    if not args.no_batch:
+        del sims
+        torch.cuda.empty_cache()
+        out["batched"] = bench_batched(args.batch_steps, 20)
+        out["batched"]["vs_plain_step"] = round(out["batched"]["MLUPS"] / value_per_form, 3)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

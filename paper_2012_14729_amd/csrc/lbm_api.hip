@@ -24,6 +24,18 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
+}  // namespace
+
+int pflbm::set_error(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+namespace {
+
 #define HIPCHK(expr)                                                                       \
   do {                                                                                     \
     hipError_t e_ = (expr);                                                                \
@@ -59,8 +71,10 @@ int validate(const lbm_params* p) {
   return LBM_OK;
 }
 
+}  // namespace
+
 // Derived coefficients (Sec. II.A Eq. 6; Sec. III after Eqs. 36 and 40).
-Phys derive(const lbm_params* p, double rho0) {
+Phys pflbm::derive_phys(const lbm_params* p, double rho0) {
   Phys c{};
   const double beta = 3.0 * p->sigma / (4.0 * p->W);
   const double kappa = 3.0 * p->W * p->sigma / 8.0;
@@ -102,6 +116,10 @@ Phys derive(const lbm_params* p, double rho0) {
   c.uw_hi_d = p->u_wall_hi;
   return c;
 }
+
+namespace {
+
+Phys derive(const lbm_params* p, double rho0) { return derive_phys(p, rho0); }
 
 struct Layout {
   Grid g;

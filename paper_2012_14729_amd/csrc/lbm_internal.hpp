@@ -74,6 +74,28 @@ struct MomentArgs {
   float* p;
 };
 
+// One instance of a batch: its step arguments for both ping-pong parities
+// (a[p] reads population buffer p and writes buffer 1 - p) and its force form.
+struct BatchInst {
+  StepArgs a[2];
+  int form;
+  int pad[3];
+};
+
+// One 64x8 tile of one instance.
+struct TileRef {
+  int inst, tx, ty, pad;
+};
+
+// Records the thread-local message returned by lbm_last_error(); returns code.
+int set_error(int code, const char* fmt, ...);
+
+}  // namespace pflbm
+struct lbm_params;
+namespace pflbm {
+// Kernel constants of a problem statement (lbm_api.hip).
+Phys derive_phys(const lbm_params* p, double rho0);
+
 // kernel launchers (lbm_kernels.hip); each returns the launch error code
 hipError_t launch_fused(int form, const StepArgs& a, hipStream_t s);
 hipError_t launch_moments(int form, const StepArgs& a, const MomentArgs& m, hipStream_t s);
@@ -84,5 +106,11 @@ hipError_t launch_init(const float* phi0, const float* ux0, const float* uy0, fl
 hipError_t launch_phi_sum(const double* phi, const Grid& g, double* partial, int npartial, double* out,
                           hipStream_t s);
 hipError_t launch_fill_int(int* p, int value, int n, hipStream_t s);
+// persistent batched step kernels over a tile list (periodic instances)
+hipError_t launch_batch_fused(const BatchInst* inst, const TileRef* tiles, int ntiles, int parity, int nblocks,
+                              hipStream_t s);
+hipError_t launch_batch_phi(const BatchInst* inst, const TileRef* tiles, int ntiles, int parity, int nblocks,
+                            hipStream_t s);
+int fused_blocks_per_cu();
 
 }  // namespace pflbm

@@ -345,13 +345,12 @@ __device__ __forceinline__ bool xcd_tile(int ntx, int nty, int& tx, int& ty) {
   return true;
 }
 
+// One 64x8 tile of the step (or of the moments): the whole per-node update
+// of a1-a12.  Called by the single-lattice kernel and the batched kernel.
 template <int FORM, bool MOMENTS, int BC>
-__global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_fused(StepArgs a, MomentArgs m) {
+__device__ __forceinline__ void fused_tile(Lds& s, const StepArgs& a, const MomentArgs& m, int tile_x, int tile_y) {
   constexpr bool WX = (BC & 1) != 0, WY = (BC & 2) != 0;   // walled axes (compile time)
-  __shared__ Lds s;
   const int tid = threadIdx.x;
-  int tile_x, tile_y;
-  if (!xcd_tile((a.g.nx + kTX - 1) / kTX, (a.g.ny + kTY - 1) / kTY, tile_x, tile_y)) return;
   const int x0 = tile_x * kTX, y0 = tile_y * kTY;
   const int lx = tid & (kTX - 1), ty = tid / kTX;   // one node per thread
   const Grid& g = a.g;
@@ -361,11 +360,10 @@ __global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(4
   const bool valid = ring_global<WX, WY>(uy_, ux_, x0, y0, a, x, y);
   const bool act = (x0 + lx < g.nx) && (y0 + ty < g.ny);
 
-  // This node's HBM reads are issued first so they complete while the LDS
-  // stencil stages run.
+  // This node's flow populations are pulled after the ring velocities (the
+  // ring threads would otherwise hold both sets of registers at once).
   float ft[9], ps[9], h[9];
   float j0 = 0.f, j1 = 0.f;
-  if (valid) load_fp<WX, WY>(a, x, y, ft, ps);
   // Stage A: phi tile with a 3-node halo (periodic wrap / even reflection at walls, Sec. IV)
   for (int k = tid; k < PH * PW; k += kFusedThreads) {
     const int py = k / PW, px = k - py * PW;
@@ -396,6 +394,7 @@ __global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(4
   }
   NodeState n;
   if (valid) {
+    load_fp<WX, WY>(a, x, y, ft, ps);
     velocity_from<FORM, true>(s, a, uy_, ux_, ft, ps, n);
     if constexpr (!MOMENTS) {
       const double ph = s.phi[uy_ + 2][ux_ + 2];
@@ -530,13 +529,21 @@ __global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(4
   }
 }
 
+template <int FORM, bool MOMENTS, int BC>
+__global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_fused(StepArgs a, MomentArgs m) {
+  __shared__ Lds s;
+  int tile_x, tile_y;
+  if (!xcd_tile((a.g.nx + kTX - 1) / kTX, (a.g.ny + kTY - 1) / kTY, tile_x, tile_y)) return;
+  fused_tile<FORM, MOMENTS, BC>(s, a, m, tile_x, tile_y);
+}
+
 // phi^{n+1}(x) = phi^n(x) + d0(x) + sum_{i>=1} h_i^+(x - c_i)   (Eq. 37, phi = sum h_i)
-__global__ __launch_bounds__(256) void k_phi(const float* __restrict__ h, double* __restrict__ phi, Grid g, int wx,
-                                             int wy) {
-  int bx, by;
-  if (!xcd_tile((g.nx + 63) / 64, (g.ny + 3) / 4, bx, by)) return;
-  const int x = bx * 64 + (threadIdx.x & 63);
-  const int y = by * 4 + (threadIdx.x >> 6);
+template <int BC>
+__device__ __forceinline__ void phi_tile(const float* __restrict__ h, double* __restrict__ phi, const Grid& g,
+                                         int tile_x, int tile_y) {
+  constexpr int wx = (BC & 1) != 0, wy = (BC & 2) != 0;
+  const int x = tile_x * kTX + (threadIdx.x & (kTX - 1));
+  const int y = tile_y * kTY + threadIdx.x / kTX;
   if (x >= g.nx || y >= g.ny) return;
   const int o = y * g.pitch + x;
   double s = (double)h[(unsigned)o];
@@ -549,6 +556,60 @@ __global__ __launch_bounds__(256) void k_phi(const float* __restrict__ h, double
   s += (double)pull<7>(h, x, y, g, wx, wy);
   s += (double)pull<8>(h, x, y, g, wx, wy);
   phi[(unsigned)o] += s;
+}
+
+template <int BC>
+__global__ __launch_bounds__(kFusedThreads) void k_phi(const float* __restrict__ h, double* __restrict__ phi, Grid g) {
+  int tx, ty;
+  if (!xcd_tile((g.nx + kTX - 1) / kTX, (g.ny + kTY - 1) / kTY, tx, ty)) return;
+  phi_tile<BC>(h, phi, g, tx, ty);
+}
+
+// Batched step: persistent workgroups walk a tile list covering every
+// instance (sorted by force form, then instance).  The list is cut into 8
+// contiguous bands, one per XCD; the workgroups of an XCD stride through its
+// band, so consecutive tiles of an instance share that XCD's L2.
+__device__ __forceinline__ void band(int ntiles, int& beg, int& end, int& first, int& stride) {
+  const int per = (ntiles + kXcds - 1) / kXcds;
+  const int xcd = blockIdx.x % kXcds;
+  beg = xcd * per;
+  end = min(ntiles, beg + per);
+  first = beg + blockIdx.x / kXcds;
+  stride = gridDim.x / kXcds;
+}
+
+__global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_fused(
+    const BatchInst* __restrict__ inst, const TileRef* __restrict__ tiles, int ntiles, int parity) {
+  __shared__ Lds s;
+  int beg, end, first, stride;
+  band(ntiles, beg, end, first, stride);
+  for (int t = first; t < end; t += stride) {
+    const TileRef tr = tiles[t];
+    const BatchInst& bi = inst[tr.inst];
+    __syncthreads();   // the previous tile is done with the LDS
+    const StepArgs& a = bi.a[parity];
+    switch (bi.form) {
+      case 0: fused_tile<0, false, 0>(s, a, MomentArgs{}, tr.tx, tr.ty); break;
+      case 1: fused_tile<1, false, 0>(s, a, MomentArgs{}, tr.tx, tr.ty); break;
+      case 2: fused_tile<2, false, 0>(s, a, MomentArgs{}, tr.tx, tr.ty); break;
+      case 3: fused_tile<3, false, 0>(s, a, MomentArgs{}, tr.tx, tr.ty); break;
+      case 4: fused_tile<4, false, 0>(s, a, MomentArgs{}, tr.tx, tr.ty); break;
+      case 5: fused_tile<5, false, 0>(s, a, MomentArgs{}, tr.tx, tr.ty); break;
+      case 6: fused_tile<6, false, 0>(s, a, MomentArgs{}, tr.tx, tr.ty); break;
+      default: fused_tile<7, false, 0>(s, a, MomentArgs{}, tr.tx, tr.ty); break;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kFusedThreads) void k_batch_phi(const BatchInst* __restrict__ inst,
+                                                             const TileRef* __restrict__ tiles, int ntiles, int parity) {
+  int beg, end, first, stride;
+  band(ntiles, beg, end, first, stride);
+  for (int t = first; t < end; t += stride) {
+    const TileRef tr = tiles[t];
+    const StepArgs& a = inst[tr.inst].a[parity];
+    phi_tile<0>(a.hout, const_cast<double*>(a.phi), a.g, tr.tx, tr.ty);
+  }
 }
 
 // Initial state, pass 1: node-local f^eq(P = 0, rho(phi0), u0) and
@@ -689,9 +750,14 @@ hipError_t launch_moments(int form, const StepArgs& a, const MomentArgs& m, hipS
 }
 
 hipError_t launch_phi(const float* h, double* phi, const Grid& g, int wall_x, int wall_y, hipStream_t s) {
-  const int nb = ((g.nx + 63) / 64) * ((g.ny + 3) / 4);
+  const int nb = ((g.nx + kTX - 1) / kTX) * ((g.ny + kTY - 1) / kTY);
   dim3 grid((nb + kXcds - 1) / kXcds * kXcds);
-  hipLaunchKernelGGL(k_phi, grid, dim3(256), 0, s, h, phi, g, wall_x, wall_y);
+  switch (wall_x | (wall_y << 1)) {
+    case 0: hipLaunchKernelGGL(k_phi<0>, grid, dim3(kFusedThreads), 0, s, h, phi, g); break;
+    case 1: hipLaunchKernelGGL(k_phi<1>, grid, dim3(kFusedThreads), 0, s, h, phi, g); break;
+    case 2: hipLaunchKernelGGL(k_phi<2>, grid, dim3(kFusedThreads), 0, s, h, phi, g); break;
+    default: hipLaunchKernelGGL(k_phi<3>, grid, dim3(kFusedThreads), 0, s, h, phi, g); break;
+  }
   return hipGetLastError();
 }
 
@@ -716,6 +782,29 @@ hipError_t launch_phi_sum(const double* phi, const Grid& g, double* partial, int
 hipError_t launch_fill_int(int* p, int value, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, s, p, value, n);
   return hipGetLastError();
+}
+
+}  // namespace pflbm
+
+namespace pflbm {
+
+hipError_t launch_batch_fused(const BatchInst* inst, const TileRef* tiles, int ntiles, int parity, int nblocks,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_fused, dim3(nblocks), dim3(kFusedThreads), 0, s, inst, tiles, ntiles, parity);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_phi(const BatchInst* inst, const TileRef* tiles, int ntiles, int parity, int nblocks,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_phi, dim3(nblocks), dim3(kFusedThreads), 0, s, inst, tiles, ntiles, parity);
+  return hipGetLastError();
+}
+
+// Resident 512-thread workgroups per CU of the batched step kernel.
+int fused_blocks_per_cu() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_fused, kFusedThreads, 0) != hipSuccess || n < 1) n = 1;
+  return n;
 }
 
 }  // namespace pflbm

@@ -85,3 +85,15 @@ def test_null_handle_rejected():
     assert lib.lbm_step(None, 1, 0, None) == _lib.LBM_E_INVAL
     assert lib.lbm_moments(None, 0, None, None, None, None, None, None) == _lib.LBM_E_INVAL
     assert lib.lbm_destroy(None) == 0
+
+
+def test_batch_rejects_walls_and_bad_forms():
+    lib = _lib.lib()
+    arr = (_lib.LbmParams * 2)(good(), good(wall_y=1))
+    n = C.c_size_t()
+    assert lib.lbm_batch_workspace_bytes(arr, 2, C.byref(n)) == _lib.LBM_E_UNSUPPORTED
+    arr = (_lib.LbmParams * 2)(good(), good(nx=4))
+    assert lib.lbm_batch_workspace_bytes(arr, 2, C.byref(n)) == _lib.LBM_E_INVAL
+    arr = (_lib.LbmParams * 2)(good(), good(nx=96))
+    assert lib.lbm_batch_workspace_bytes(arr, 2, C.byref(n)) == 0 and n.value > 0
+    assert lib.lbm_batch_workspace_bytes(arr, 0, C.byref(n)) == _lib.LBM_E_INVAL
