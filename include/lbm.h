@@ -155,6 +155,41 @@ int lbm_batch_moments(lbm_batch* batch, int32_t k, float* d_phi, float* d_rho, f
 int lbm_batch_status(lbm_batch* batch, int32_t* h_flags, void* stream);
 int lbm_batch_destroy(lbm_batch* batch);
 
+/* ------------------------------------------------------------------------
+ * Adjoint.  The adjoint state lambda of a step is dL/ds for the physical
+ * pre-collision state s = (f_0..f_8, h_0..h_8, J_x, J_y) of every node: 20
+ * FP64 planes of nx*ny values, row-major (x fastest), plane order f, h, J.
+ * An lbm_adj is bound to one simulation and differentiates its current
+ * state; it keeps per-node accumulators of dL/dsigma and dL/dM.
+ * The workspace (FP64 scratch for the recomputed step and its adjoint) is
+ * caller-owned, 256-byte aligned, lbm_adjoint_workspace_bytes long.
+ * ------------------------------------------------------------------------ */
+typedef struct lbm_adj lbm_adj;
+int lbm_adjoint_workspace_bytes(const lbm_params* p, size_t* bytes);
+/* Requires p->sigma > 0 (dL/dsigma is formed as dL/dF * F / sigma). Zeroes
+ * the parameter-gradient accumulators (asynchronously on the null stream). */
+int lbm_adjoint_create(lbm_adj** adj, lbm_sim* sim, void* d_ws, size_t ws_bytes);
+/* Zero the dL/dsigma, dL/dM accumulators. */
+int lbm_adjoint_reset(lbm_adj* adj, void* stream);
+/* lambda_T for L = 1/2 sum_x (phi_T - phi*)^2 at the simulation's current
+ * state (reading A19): dL/dh_i = phi_T - phi*, dL/df = dL/dJ = 0.  d_target:
+ * nx*ny FP32.  If h_loss is not NULL the call synchronises and stores L. */
+int lbm_adjoint_seed_phi_misfit(lbm_adj* adj, const float* d_target, double* d_lambda, double* h_loss,
+                                void* stream);
+/* One step backwards: the simulation must hold the forward state s_t of the
+ * step being differentiated (restore it first).  In: lambda_{t+1}; out
+ * (in place): lambda_t = (ds_{t+1}/ds_t)^T lambda_{t+1}.  Adds this step's
+ * contributions to dL/dsigma and dL/dM (Eqs. 6, 29-37, 41-43). */
+int lbm_adjoint_step(lbm_adj* adj, int32_t force_form, double* d_lambda, void* stream);
+/* Adjoint of lbm_init (reading A11): dL/dphi0 (nx*ny FP64) from lambda_0,
+ * adding the initial state's contributions to dL/dsigma and dL/dM.  phi0,
+ * u0 as given to lbm_init. */
+int lbm_adjoint_init(lbm_adj* adj, const float* d_phi0, const float* d_ux0, const float* d_uy0,
+                     const double* d_lambda0, double* d_dphi0, void* stream);
+/* Synchronises; returns the accumulated dL/dsigma and dL/dM. */
+int lbm_adjoint_param_grads(lbm_adj* adj, double* h_dsigma, double* h_dM, void* stream);
+int lbm_adjoint_destroy(lbm_adj* adj);
+
 const char* lbm_last_error(void);
 const char* lbm_version(void);
 

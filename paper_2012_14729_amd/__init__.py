@@ -17,7 +17,7 @@ import torch
 
 from ._lib import FORMS, LbmError, check, form_index, lib, make_params
 
-__all__ = ["Simulation", "Batch", "FORMS", "LbmError", "params_struct"]
+__all__ = ["Simulation", "Batch", "Adjoint", "rollout", "check_lambda", "FORMS", "LbmError", "params_struct"]
 
 
 def params_struct(p):
@@ -38,6 +38,23 @@ def _stream(stream):
 
 def _ptr(t):
     return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def check_lambda(lam, ny, nx, device):
+    """The adjoint entry points read and write 20 * nx * ny doubles through
+    this pointer: refuse anything but a contiguous float64 [20, ny, nx]
+    tensor on the simulation's device."""
+    if not torch.is_tensor(lam):
+        raise TypeError("lambda must be a torch tensor")
+    if lam.dtype != torch.float64:
+        raise TypeError(f"lambda must be float64, got {lam.dtype}")
+    if tuple(lam.shape) != (20, ny, nx):
+        raise ValueError(f"lambda shape {tuple(lam.shape)} != (20, {ny}, {nx})")
+    if not lam.is_contiguous():
+        raise ValueError("lambda must be contiguous")
+    if lam.device != torch.device(device):
+        raise ValueError(f"lambda is on {lam.device}, the simulation on {device}")
+    return lam
 
 
 def _field(x, ny, nx, device):
@@ -174,3 +191,129 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Adjoint:
+    """Adjoint of the step of one Simulation (lbm_adjoint_*).  The adjoint
+    state is a float64 tensor [20, ny, nx]: dL/df_0..8, dL/dh_0..8, dL/dJ of
+    the physical pre-collision state."""
+
+    def __init__(self, sim: Simulation):
+        L = lib()
+        self.sim = sim
+        n = C.c_size_t()
+        check(L.lbm_adjoint_workspace_bytes(C.byref(sim.params), C.byref(n)))
+        self.workspace = torch.empty(n.value, dtype=torch.uint8, device=sim.workspace.device)
+        h = C.c_void_p()
+        check(L.lbm_adjoint_create(C.byref(h), sim._h, _ptr(self.workspace), n.value))
+        self._h = h
+
+    def new_lambda(self):
+        return torch.zeros((20, self.sim.ny, self.sim.nx), dtype=torch.float64, device=self.workspace.device)
+
+    def seed_phi_misfit(self, target, stream=None):
+        t = _field(target, self.sim.ny, self.sim.nx, self.workspace.device)
+        lam = self.new_lambda()
+        loss = C.c_double()
+        check(lib().lbm_adjoint_seed_phi_misfit(self._h, _ptr(t), _ptr(lam), C.byref(loss), _stream(stream)))
+        return lam, loss.value
+
+    def step(self, lam, form, stream=None):
+        check_lambda(lam, self.sim.ny, self.sim.nx, self.workspace.device)
+        check(lib().lbm_adjoint_step(self._h, form_index(form), _ptr(lam), _stream(stream)))
+        return lam
+
+    def init(self, lam, phi0, ux0=None, uy0=None, stream=None):
+        dev = self.workspace.device
+        check_lambda(lam, self.sim.ny, self.sim.nx, dev)
+        p = _field(phi0, self.sim.ny, self.sim.nx, dev)
+        ux = _field(ux0, self.sim.ny, self.sim.nx, dev)
+        uy = _field(uy0, self.sim.ny, self.sim.nx, dev)
+        if (ux is None) != (uy is None):
+            ux = torch.zeros_like(p) if ux is None else ux
+            uy = torch.zeros_like(p) if uy is None else uy
+        d = torch.empty((self.sim.ny, self.sim.nx), dtype=torch.float64, device=dev)
+        check(lib().lbm_adjoint_init(self._h, _ptr(p), _ptr(ux), _ptr(uy), _ptr(lam), _ptr(d), _stream(stream)))
+        return d
+
+    def param_grads(self, stream=None):
+        ds, dm = C.c_double(), C.c_double()
+        check(lib().lbm_adjoint_param_grads(self._h, C.byref(ds), C.byref(dm), _stream(stream)))
+        return ds.value, dm.value
+
+    def reset(self, stream=None):
+        check(lib().lbm_adjoint_reset(self._h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lbm_adjoint_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _run_adjoint(params, form, T, phi0, ux0, uy0, target, every):
+    """Forward T steps with checkpoints every `every` steps, then the adjoint
+    backwards, recomputing each segment's states from its checkpoint.
+    Returns (loss, dphi0, dsigma, dM)."""
+    sim = Simulation(params, phi0, ux0, uy0, device=phi0.device)
+    adj = Adjoint(sim)
+    ckpt = []
+    for t in range(T):
+        if t % every == 0:
+            ckpt.append(sim.save())
+        sim.step(1, form)
+    lam, loss = adj.seed_phi_misfit(target)
+    nseg = len(ckpt)
+    for s in reversed(range(nseg)):
+        t0, t1 = s * every, min(T, (s + 1) * every)
+        sim.restore(ckpt[s])
+        states = []
+        for t in range(t0, t1):
+            states.append(sim.save())
+            if t < t1 - 1:
+                sim.step(1, form)
+        for t in reversed(range(t0, t1)):
+            sim.restore(states[t - t0])
+            adj.step(lam, form)
+        del states
+    dphi0 = adj.init(lam, phi0, ux0, uy0)
+    dsig, dM = adj.param_grads()
+    return loss, dphi0, dsig, dM
+
+
+class _Rollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, phi0, sigma, M, params, form, T, target, ux0, uy0, every):
+        p = dict(params)
+        p["sigma"] = float(sigma)
+        p["M"] = float(M)
+        loss, dphi0, dsig, dM = _run_adjoint(p, form, T, phi0.detach().float(), ux0, uy0, target, every)
+        ctx.save_for_backward(dphi0)
+        ctx.dsig, ctx.dM = dsig, dM
+        return torch.tensor(loss, dtype=torch.float64, device=phi0.device)
+
+    @staticmethod
+    def backward(ctx, g):
+        (dphi0,) = ctx.saved_tensors
+        g = g.to(torch.float64)
+        return ((g * dphi0).to(torch.float32), (g * ctx.dsig).reshape(()), (g * ctx.dM).reshape(()),
+                None, None, None, None, None, None, None)
+
+
+def rollout(phi0, sigma, M, params, form, T, target, ux0=None, uy0=None, every=None):
+    """L = 1/2 sum (phi_T - phi*)^2 after T steps from phi0 with surface
+    tension sigma and mobility M (other parameters from `params`), as a
+    differentiable scalar: gradients w.r.t. phi0, sigma and M come from the
+    hand-written adjoint with checkpoints every ceil(sqrt(T)) steps.  The
+    adjoint pass runs inside the forward call; backward only scales it."""
+    if every is None:
+        every = max(1, int(math.ceil(math.sqrt(T))))
+    sig = sigma if torch.is_tensor(sigma) else torch.tensor(float(sigma), dtype=torch.float64)
+    m = M if torch.is_tensor(M) else torch.tensor(float(M), dtype=torch.float64)
+    pd = params if isinstance(params, dict) else {k: getattr(params, k) for k in params.__dataclass_fields__}
+    return _Rollout.apply(phi0, sig, m, pd, form, int(T), target, ux0, uy0, int(every))

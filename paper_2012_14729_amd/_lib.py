@@ -61,6 +61,15 @@ _SIGS = {
                                     C.c_void_p, C.c_void_p]),
     "lbm_batch_status": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_void_p]),
     "lbm_batch_destroy": (C.c_int, [C.c_void_p]),
+    "lbm_adjoint_workspace_bytes": (C.c_int, [C.POINTER(LbmParams), C.POINTER(C.c_size_t)]),
+    "lbm_adjoint_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p, C.c_size_t]),
+    "lbm_adjoint_reset": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lbm_adjoint_seed_phi_misfit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
+    "lbm_adjoint_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "lbm_adjoint_init": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p]),
+    "lbm_adjoint_param_grads": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]),
+    "lbm_adjoint_destroy": (C.c_int, [C.c_void_p]),
     "lbm_last_error": (C.c_char_p, []),
     "lbm_version": (C.c_char_p, []),
 }

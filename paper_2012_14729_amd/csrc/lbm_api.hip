@@ -229,6 +229,29 @@ int timer_stop(lbm_sim* s, int k, int j, hipStream_t st) {
 
 }  // namespace
 
+int pflbm::sim_params(const lbm_sim* s, lbm_params* out) {
+  if (!s || !out) return fail(LBM_E_INVAL, "NULL argument");
+  *out = s->p;
+  return LBM_OK;
+}
+
+void pflbm::sim_grid(const lbm_sim* s, int* pitch, long long* ps) {
+  *pitch = s->L.g.pitch;
+  *ps = s->L.g.ps;
+}
+
+Phys pflbm::sim_phys(const lbm_sim* s) { return s->c; }
+
+int pflbm::sim_view(const lbm_sim* s, SimView* v) {
+  if (!s || !v) return fail(LBM_E_INVAL, "NULL argument");
+  v->f = s->f(s->cur);
+  v->P = s->P(s->cur);
+  v->h = s->h(s->cur);
+  v->J = s->J();
+  v->phi = s->phi();
+  return LBM_OK;
+}
+
 extern "C" {
 
 const char* lbm_last_error(void) { return g_err; }

@@ -96,6 +96,22 @@ namespace pflbm {
 // Kernel constants of a problem statement (lbm_api.hip).
 Phys derive_phys(const lbm_params* p, double rho0);
 
+}  // namespace pflbm
+struct lbm_sim;
+namespace pflbm {
+// Read access to a single lattice's current state (lbm_api.hip).
+struct SimView {
+  const float* f;     // 9 planes: f_i - w_i P of the storing node
+  const float* P;     // pressure of the storing node
+  const float* h;     // 9 planes (slot 0: d0)
+  const float* J;     // 2 planes
+  const double* phi;  // order parameter (current)
+};
+int sim_params(const lbm_sim* s, lbm_params* out);
+void sim_grid(const lbm_sim* s, int* pitch, long long* ps);
+Phys sim_phys(const lbm_sim* s);
+int sim_view(const lbm_sim* s, SimView* v);
+
 // kernel launchers (lbm_kernels.hip); each returns the launch error code
 hipError_t launch_fused(int form, const StepArgs& a, hipStream_t s);
 hipError_t launch_moments(int form, const StepArgs& a, const MomentArgs& m, hipStream_t s);

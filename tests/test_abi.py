@@ -97,3 +97,22 @@ def test_batch_rejects_walls_and_bad_forms():
     arr = (_lib.LbmParams * 2)(good(), good(nx=96))
     assert lib.lbm_batch_workspace_bytes(arr, 2, C.byref(n)) == 0 and n.value > 0
     assert lib.lbm_batch_workspace_bytes(arr, 0, C.byref(n)) == _lib.LBM_E_INVAL
+
+
+def test_adjoint_lambda_guard_refuses_what_would_overrun_the_buffer():
+    """lbm_adjoint_step reads and writes 20 nx ny doubles through lambda: the
+    binding refuses any tensor that does not hold exactly that."""
+    import torch
+    from paper_2012_14729_amd import check_lambda
+    ok = torch.zeros((20, 6, 8), dtype=torch.float64)
+    assert check_lambda(ok, 6, 8, "cpu") is ok
+    with pytest.raises(TypeError):
+        check_lambda(ok.float(), 6, 8, "cpu")          # float32: half the bytes
+    with pytest.raises(ValueError):
+        check_lambda(torch.zeros((20, 6, 7), dtype=torch.float64), 6, 8, "cpu")
+    with pytest.raises(ValueError):
+        check_lambda(torch.zeros((20, 8, 6), dtype=torch.float64).transpose(1, 2), 6, 8, "cpu")
+    with pytest.raises(ValueError):
+        check_lambda(ok, 6, 8, "cuda:0")
+    with pytest.raises(TypeError):
+        check_lambda(ok.numpy(), 6, 8, "cpu")

@@ -1,0 +1,137 @@
+"""GPU adjoint (lbm_adjoint_*) against the oracle's adjoint (torch autograd
+through the FP64 oracle, itself pinned by finite differences and complex
+step in test_oracle_adjoint.py)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as WL
+from oracle import lbm_ref as R
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def oracle_params(p):
+    d = p.as_dict()
+    d["rho0"] = None
+    return R.Params(**d)
+
+
+def t64(a):
+    return None if a is None else torch.tensor(np.asarray(a, np.float32), dtype=torch.float64)
+
+
+CASES = {
+    "shear_walls": lambda: WL.config_shear(nx=32, ny=16, R=4.0, Re=1.0, Ca=0.2),
+    "periodic_drop": lambda: (WL.ParamSet(nx=24, ny=20, rho1=5.0, rho2=1.0, nu1=0.1, nu2=0.2, sigma=0.01, W=3.0,
+                                          M=0.05, tau_h=0.9), WL.droplet(24, 20, 5.0, 3.0, 10.3, 9.2), None, None),
+    "box_gravity": lambda: (WL.ParamSet(nx=20, ny=24, wall_x=1, wall_y=1, rho1=3.0, rho2=1.0, nu1=0.1, nu2=0.1,
+                                        sigma=0.01, W=3.0, M=0.05, tau_h=0.9, gx=2e-5, gy=-3e-5),
+                            WL.droplet(20, 24, 5.0, 3.0, 9.6, 12.3), None, None),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("form", ["stf1", "stf2", "cpf1", "cpf2", "pf1", "pf2", "csf1", "csf2"])
+def test_one_adjoint_step_matches_oracle_vjp(case, form):
+    import paper_2012_14729_amd as P
+    p, phi0, ux0, uy0 = CASES[case]()
+    k = 4
+    op = oracle_params(p)
+    sig = torch.tensor(op.sigma, requires_grad=True)
+    M = torch.tensor(op.M, requires_grad=True)
+    st = R.run(R.init(op, t64(phi0), t64(ux0), t64(uy0)), form, op, k)
+    f = st["f"].clone().requires_grad_(True)
+    h = st["h"].clone().requires_grad_(True)
+    J = st["J"].clone().requires_grad_(True)
+    q = R.Params(**{**op.__dict__, "sigma": sig, "M": M})
+    nxt = R.step(dict(f=f, h=h, J=J, rho0=st["rho0"], t=k), form, q)
+    out = torch.cat([nxt["f"], nxt["h"], nxt["J"]])
+    g = torch.Generator().manual_seed(17)
+    lam1 = torch.randn(out.shape, generator=g, dtype=torch.float64)
+    gf, gh, gJ, gs, gm = torch.autograd.grad(out, (f, h, J, sig, M), grad_outputs=lam1)
+    ref = torch.cat([gf, gh, gJ]).numpy()
+
+    # dL/dsigma and dL/dM are sums of signed per-node terms that can nearly
+    # cancel (PF-2 on the sheared drop).  The GPU evaluates them at its own
+    # FP32-stored state, ~1e-7 away from the oracle's (storage rounding), so
+    # each summed term may move by ~1e-7 of itself: the bound adds 1e-7 of the
+    # size of the summed terms, sum_j |d out_j / d theta| |lambda_j|, with the
+    # derivative vector from a central difference of the oracle step.
+    def term_scale(name):
+        v = float(getattr(op, name))
+        d = 1e-6 * v
+        outs = []
+        with torch.no_grad():
+            for s in (1, -1):
+                qq = R.Params(**{**op.__dict__, name: v + s * d})
+                nn = R.step(dict(f=st["f"], h=st["h"], J=st["J"], rho0=st["rho0"], t=k), form, qq)
+                outs.append(torch.cat([nn["f"], nn["h"], nn["J"]]))
+        return float(((outs[0] - outs[1]).abs() / (2 * d) * lam1.abs()).sum())
+
+    scale_s, scale_m = term_scale("sigma"), term_scale("M")
+
+    sim = P.Simulation(p.as_dict(), np.asarray(phi0, np.float32), ux0, uy0)
+    sim.step(k, form)
+    adj = P.Adjoint(sim)
+    lam = lam1.to("cuda")
+    adj.step(lam, form)
+    got = lam.cpu().numpy()
+    ds, dm = adj.param_grads()
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"[adjoint-step] {case} {form}: rel err {err:.2e} dsig {ds:.6e}/{float(gs):.6e} dM {dm:.6e}/{float(gm):.6e} "
+          f"term scales {scale_s:.3e} {scale_m:.3e}",
+          flush=True)
+    assert err < 1e-5
+    assert abs(ds - float(gs)) <= 1e-5 * abs(float(gs)) + 1e-7 * scale_s
+    assert abs(dm - float(gm)) <= 1e-5 * abs(float(gm)) + 1e-7 * scale_m
+
+
+@pytest.mark.parametrize("form", ["stf2", "cpf2", "csf1"])
+def test_rollout_gradients_match_oracle(form):
+    """Shear drop 64x32 (R = 8), 120 steps, target from the forward run at
+    1.1 sigma; sqrt(T) checkpoints.  Bound 1e-4: the seed phi_T - phi* is a
+    small difference (|r| ~ 1e-3) of fields the GPU stores in FP32, so its
+    relative error is ~1e-7 / 1e-3 before the 120 adjoint steps."""
+    import paper_2012_14729_amd as P
+    p, phi0, ux0, uy0 = WL.config_shear(nx=64, ny=32, R=8.0, Re=1.0, Ca=0.2)
+    T = 120
+    op = oracle_params(p)
+    phi0_64, ux_64, uy_64 = t64(phi0), t64(ux0), t64(uy0)
+    with torch.no_grad():
+        q = R.Params(**{**op.__dict__, "sigma": op.sigma * 1.1})
+        target = R.run(R.init(q, phi0_64, ux_64, uy_64), form, q, T)["h"].sum(0)
+    sig = torch.tensor(op.sigma, requires_grad=True)
+    M = torch.tensor(op.M, requires_grad=True)
+    ph = phi0_64.clone().requires_grad_(True)
+    q = R.Params(**{**op.__dict__, "sigma": sig, "M": M})
+    phiT = R.run(R.init(q, ph, ux_64, uy_64), form, q, T)["h"].sum(0)
+    Lref = 0.5 * ((phiT - target) ** 2).sum()
+    Lref.backward()
+
+    dev = torch.device("cuda")
+    phi0_t = torch.tensor(np.asarray(phi0, np.float32), device=dev, requires_grad=True)
+    sig_t = torch.tensor(op.sigma, dtype=torch.float64, requires_grad=True)
+    M_t = torch.tensor(op.M, dtype=torch.float64, requires_grad=True)
+    tgt = target.float().to(dev)
+    L = P.rollout(phi0_t, sig_t, M_t, p.as_dict(), form, T, tgt,
+                  ux0=torch.tensor(np.asarray(ux0, np.float32), device=dev),
+                  uy0=torch.tensor(np.asarray(uy0, np.float32), device=dev))
+    L.backward()
+    e_s = abs(float(sig_t.grad) - float(sig.grad)) / abs(float(sig.grad))
+    e_m = abs(float(M_t.grad) - float(M.grad)) / abs(float(M.grad))
+    gp = phi0_t.grad.double().cpu().numpy()
+    rp = ph.grad.numpy()
+    e_p = np.abs(gp - rp).max() / np.abs(rp).max()
+    print(f"[rollout] {form}: L {float(L):.6e}/{float(Lref):.6e} e_sigma {e_s:.2e} e_M {e_m:.2e} e_phi0 {e_p:.2e}",
+          flush=True)
+    assert abs(float(L) - float(Lref)) <= 1e-4 * float(Lref)
+    assert e_s < 1e-4 and e_m < 1e-4 and e_p < 1e-4
