@@ -124,6 +124,57 @@ def bench_batched(steps, loop_steps):
             "speedup_vs_loop": round(batched / loop, 2), "unstable_instances": unstable}
 
 
+def bench_adjoint(T):
+    """Gradient of L = 1/2 sum (phi_T - phi*)^2 w.r.t. phi0, sigma and M for
+    the drop in simple shear (512x256, walls at +-U, R = 64, Re = 1,
+    Ca = 0.2, STF-2), phi* from the forward run at 1.1 sigma, T steps with
+    checkpoints every ceil(sqrt(T)) steps.  Reported against the plain step
+    on the same configuration."""
+    import numpy as np
+    import torch
+
+    import paper_2012_14729_amd as P
+    import workloads as WL
+
+    dev = torch.device("cuda:0")
+    p, phi0, ux0, uy0 = WL.config_shear()
+    pd = p.as_dict()
+    cells = p.nx * p.ny
+    phi0 = torch.tensor(np.asarray(phi0, np.float32), device=dev)
+    ux = torch.tensor(np.asarray(ux0, np.float32), device=dev)
+    uy = torch.tensor(np.asarray(uy0, np.float32), device=dev)
+    print(f"[bench] adjoint: shear {p.nx}x{p.ny}, T={T}", file=sys.stderr, flush=True)
+    tgt_p = dict(pd, sigma=1.1 * pd["sigma"])
+    s = P.Simulation(tgt_p, phi0, ux, uy, device=dev)
+    s.step(T, "stf2")
+    target = s.moments("stf2")["phi"]
+    del s
+    s = P.Simulation(pd, phi0, ux, uy, device=dev)
+    s.step(50, "stf2")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(T, "stf2")
+    torch.cuda.synchronize()
+    plain = cells * T / (time.perf_counter() - t0) / 1e6
+    del s
+    P.adjoint_gradients(pd, "stf2", 16, phi0, target, ux, uy)   # warm-up
+    tm = {}
+    loss, dphi0, dsig, dM = P.adjoint_gradients(pd, "stf2", T, phi0, target, ux, uy, timings=tm)
+    fwd = cells * T / tm["forward_s"] / 1e6
+    bwd = cells * T / tm["backward_s"] / 1e6
+    tot = cells * T / (tm["forward_s"] + tm["backward_s"]) / 1e6
+    print(f"[bench] adjoint: forward {tm['forward_s']:.3f} s, backward {tm['backward_s']:.3f} s", file=sys.stderr,
+          flush=True)
+    return {"workload": f"drop in shear {p.nx}x{p.ny}, walls +-U, R=64, Re=1, Ca=0.2, STF-2, T={T}, "
+                        f"checkpoints every {tm['every']} steps",
+            "plain_step_MLUPS": round(plain, 1),
+            "forward_with_checkpoints_MLUPS": round(fwd, 1),
+            "backward_MLUPS": round(bwd, 1), "gradient_MLUPS": round(tot, 1),
+            "backward_vs_plain_step": round(bwd / plain, 3), "gradient_vs_plain_step": round(tot / plain, 3),
+            "backward_note": "adjoint steps (FP64) plus the recompute of each segment from its checkpoint",
+            "loss": loss, "dL_dsigma": dsig, "dL_dM": dM, "max_abs_dL_dphi0": float(dphi0.abs().max())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +184,8 @@ def main():
     ap.add_argument("--size", type=int, default=2048)
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=4000)
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (multi-GPU sharding is a "
@@ -208,7 +261,7 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"stationary droplet {p.nx}x{p.ny} periodic, R={p.nx // 8}, W=5, rho1/rho2=1000, "
                                f"mu1/mu2=100, sigma=1e-3, 8 force forms round-robin",
-                   "precision": "FP32 populations and collision; FP64 order parameter and stencil/force stage",
+                   "precision": "FP32 storage of f, h, J, P; FP64 arithmetic (collision, stencils, forces) and FP64 phi",
                    "step_bytes_per_node": BYTES_FUSED + BYTES_PHI,
                    "step_GBs": round((BYTES_FUSED + BYTES_PHI) * value * 1e6 / 1e9, 1)},
         "roofline": roofline,
@@ -224,6 +277,9 @@ def main():
         torch.cuda.empty_cache()
         out["batched"] = bench_batched(args.batch_steps, 20)
         out["batched"]["vs_plain_step"] = round(out["batched"]["MLUPS"] / value_per_form, 3)
+    if not args.no_adjoint:
+        torch.cuda.empty_cache()
+        out["adjoint"] = bench_adjoint(args.adjoint_steps)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

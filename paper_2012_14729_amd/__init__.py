@@ -12,12 +12,13 @@ from __future__ import annotations
 
 import ctypes as C
 import math
+import time
 
 import torch
 
 from ._lib import FORMS, LbmError, check, form_index, lib, make_params
 
-__all__ = ["Simulation", "Batch", "Adjoint", "rollout", "check_lambda", "FORMS", "LbmError", "params_struct"]
+__all__ = ["Simulation", "Batch", "Adjoint", "rollout", "adjoint_gradients", "check_lambda", "FORMS", "LbmError", "params_struct"]
 
 
 def params_struct(p):
@@ -256,10 +257,21 @@ class Adjoint:
             pass
 
 
-def _run_adjoint(params, form, T, phi0, ux0, uy0, target, every):
-    """Forward T steps with checkpoints every `every` steps, then the adjoint
-    backwards, recomputing each segment's states from its checkpoint.
-    Returns (loss, dphi0, dsigma, dM)."""
+def adjoint_gradients(params, form, T, phi0, target, ux0=None, uy0=None, every=None, timings=None):
+    """dL/dphi0, dL/dsigma, dL/dM of L = 1/2 sum (phi_T - target)^2.
+
+    Forward T steps keeping a state checkpoint every `every` steps (default
+    ceil(sqrt(T))), then the adjoint backwards: each segment is recomputed
+    from its checkpoint (one state per step, held for that segment only) and
+    the adjoint steps run over it in reverse.  Memory: (T/every + every)
+    states.  `timings`, if a dict, receives the forward and backward wall
+    times (seconds, synchronised).  Returns (loss, dphi0 [float64], dsigma, dM)."""
+    if every is None:
+        every = max(1, int(math.ceil(math.sqrt(T))))
+    sync = timings is not None
+    if sync:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
     sim = Simulation(params, phi0, ux0, uy0, device=phi0.device)
     adj = Adjoint(sim)
     ckpt = []
@@ -268,21 +280,29 @@ def _run_adjoint(params, form, T, phi0, ux0, uy0, target, every):
             ckpt.append(sim.save())
         sim.step(1, form)
     lam, loss = adj.seed_phi_misfit(target)
-    nseg = len(ckpt)
-    for s in reversed(range(nseg)):
-        t0, t1 = s * every, min(T, (s + 1) * every)
+    if sync:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    for s in reversed(range(len(ckpt))):
+        t_lo, t_hi = s * every, min(T, (s + 1) * every)
         sim.restore(ckpt[s])
         states = []
-        for t in range(t0, t1):
+        for t in range(t_lo, t_hi):
             states.append(sim.save())
-            if t < t1 - 1:
+            if t < t_hi - 1:
                 sim.step(1, form)
-        for t in reversed(range(t0, t1)):
-            sim.restore(states[t - t0])
+        for t in reversed(range(t_lo, t_hi)):
+            sim.restore(states[t - t_lo])
             adj.step(lam, form)
         del states
     dphi0 = adj.init(lam, phi0, ux0, uy0)
     dsig, dM = adj.param_grads()
+    if sync:
+        torch.cuda.synchronize()
+        timings["forward_s"] = t1 - t0
+        timings["backward_s"] = time.perf_counter() - t1
+        timings["checkpoints"] = len(ckpt)
+        timings["every"] = every
     return loss, dphi0, dsig, dM
 
 
@@ -292,7 +312,7 @@ class _Rollout(torch.autograd.Function):
         p = dict(params)
         p["sigma"] = float(sigma)
         p["M"] = float(M)
-        loss, dphi0, dsig, dM = _run_adjoint(p, form, T, phi0.detach().float(), ux0, uy0, target, every)
+        loss, dphi0, dsig, dM = adjoint_gradients(p, form, T, phi0.detach().float(), target, ux0, uy0, every)
         ctx.save_for_backward(dphi0)
         ctx.dsig, ctx.dM = dsig, dM
         return torch.tensor(loss, dtype=torch.float64, device=phi0.device)
