@@ -258,7 +258,7 @@ def main():
         "metric": "MLUPS & HBM GB/s (% peak) FP32 1 GPU; batched/adjoint vs plain step",
         "value": round(value, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(el / args.steps * 1e3, 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"stationary droplet {p.nx}x{p.ny} periodic, R={p.nx // 8}, W=5, rho1/rho2=1000, "
                                f"mu1/mu2=100, sigma=1e-3, 8 force forms round-robin",
                    "precision": "FP32 storage of f, h, J, P; FP64 arithmetic (collision, stencils, forces) and FP64 phi",

@@ -138,3 +138,11 @@ def test_merging_pair_csf1():
     p = WL.ParamSet(nx=96, ny=64, rho1=10.0, rho2=1.0, nu1=0.1, nu2=0.1, sigma=3e-3, W=4.0, M=0.1, tau_h=0.8)
     phi0 = WL.two_droplets(96, 64, 14.0, 10.0, 2.0, 4.0)
     check(p, phi0, None, None, "csf1", 300)
+
+
+@pytest.mark.parametrize("form", ["stf1", "stf2", "cpf1", "cpf2", "pf1", "pf2", "csf1", "csf2"])
+def test_droplet256_density_ratio_1000(form):
+    """The large stationary droplet at the oracle's size: 256x256 periodic,
+    R = 32, W = 5, rho1/rho2 = 1000, mu1/mu2 = 100, sigma = 1e-3, 100 steps."""
+    p, phi0, ux0, uy0 = WL.config_droplet_large(256)
+    check(p, phi0, ux0, uy0, form, 100)
