@@ -94,7 +94,11 @@ int lbm_workspace_bytes(const lbm_params* p, size_t* bytes);
  * h = h^eq(phi0, mu_phi(phi0), u0), (phi u)^(-1) = phi0 u0 (Eqs. 31-32).
  * If p->rho0 is NaN the call synchronises `stream` once to fix rho0.
  * The workspace must stay allocated until lbm_destroy.  The inputs may be
- * freed when the call returns (they are consumed on `stream`). */
+ * freed when the call returns (they are consumed on `stream`).
+ * Tiles away from the domain edge use a faster addressing path with the
+ * same arithmetic; the environment variable PFLBM_GENERAL_PATH=1, read here
+ * and by lbm_batch_create, sends every tile through the general path
+ * (diagnostics: both paths give bitwise identical states). */
 int lbm_init(lbm_sim** sim, const lbm_params* p, void* d_ws, size_t ws_bytes,
              const float* d_phi0, const float* d_ux0, const float* d_uy0, void* stream);
 
@@ -118,10 +122,12 @@ int lbm_status(lbm_sim* sim, int32_t* diverged, void* stream);
 /* Number of completed time steps since init (host counter). */
 int lbm_get_step(const lbm_sim* sim, int64_t* step);
 
-/* Checkpoint: the complete state (populations, FP64 order parameter, (phi u)
- * history, step counter) copied to/from a caller-owned device blob of
- * lbm_state_bytes bytes.  Restoring and stepping reproduces an uninterrupted
- * run bit for bit. */
+/* Checkpoint: the complete device state (populations, pressure, FP64 order
+ * parameter, (phi u) history, divergence flag) copied to/from a caller-owned
+ * device blob of lbm_state_bytes bytes; the blob's unused tail is written as
+ * zeros, so equal states give equal blobs.  Restoring and stepping
+ * reproduces an uninterrupted run bit for bit.  The host step counter
+ * (lbm_get_step) is not part of the blob and restore leaves it unchanged. */
 int lbm_state_bytes(const lbm_sim* sim, size_t* bytes);
 int lbm_save(lbm_sim* sim, void* d_blob, void* stream);
 int lbm_restore(lbm_sim* sim, const void* d_blob, void* stream);

@@ -22,6 +22,9 @@ ARCH = os.environ.get("PFLBM_ARCH", "gfx950")
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds fuse only where one source expression holds both, so a
+    # node's arithmetic does not depend on which code path its tile takes
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
 ]
 

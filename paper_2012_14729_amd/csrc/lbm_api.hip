@@ -2,6 +2,7 @@
 // derived constants, workspace layout, launch sequencing, checkpoints and
 // kernel timing.  Declarations and semantics: include/lbm.h.
 #include <cmath>
+#include <cstdlib>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -135,6 +136,9 @@ Layout layout_for(const lbm_params* p) {
   L.g.pitch = (int)align_up((size_t)p->nx, 64);
   L.g.ps = (long long)L.g.pitch * p->ny;
   L.g.psi = (int)L.g.ps;
+  L.g.fast = 36LL * L.g.ps < (1LL << 32) ? 1 : 0;
+  if (const char* e = std::getenv("PFLBM_GENERAL_PATH"))   // diagnostics: every tile on the general path
+    if (e[0] == '1') L.g.fast = 0;
   const size_t plane = (size_t)L.g.ps * sizeof(float);
   size_t o = 0;
   for (int b = 0; b < 2; ++b) { L.off_f[b] = o; o = align_up(o + 9 * plane, kAlign); }
@@ -375,6 +379,9 @@ int lbm_save(lbm_sim* s, void* d_blob, void* stream) {
   HIPCHK(hipMemcpyAsync(b + 21 * plane, s->phi(), (size_t)s->L.g.ps * sizeof(double), hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(b + 21 * plane + (size_t)s->L.g.ps * sizeof(double), s->status(), sizeof(int),
                         hipMemcpyDeviceToDevice, st));
+  // the rest of the blob is zero, so equal states give equal blobs
+  constexpr int kTailInts = (int)((kAlign - sizeof(int)) / sizeof(int));
+  HIPCHK(launch_fill_int((int*)(b + 21 * plane + (size_t)s->L.g.ps * sizeof(double) + sizeof(int)), 0, kTailInts, st));
   return LBM_OK;
 }
 

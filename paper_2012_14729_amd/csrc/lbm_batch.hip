@@ -11,6 +11,7 @@
 // launch per kChunk steps.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstdarg>
 #include <cstdio>
 #include <new>
@@ -70,6 +71,9 @@ BatchLayout layout(const lbm_params* p, int count) {
     I.g.pitch = (p[k].nx + 63) / 64 * 64;   // as a single lattice, so results match bit for bit
     I.g.ps = (long long)I.g.pitch * p[k].ny;
     I.g.psi = (int)I.g.ps;
+    I.g.fast = 36LL * I.g.ps < (1LL << 32) ? 1 : 0;
+    if (const char* e = std::getenv("PFLBM_GENERAL_PATH"))
+      if (e[0] == '1') I.g.fast = 0;
     const size_t plane = (size_t)I.g.ps * sizeof(float);
     for (int b = 0; b < 2; ++b) { I.f[b] = o; o = up(o + 9 * plane); }
     for (int b = 0; b < 2; ++b) { I.h[b] = o; o = up(o + 9 * plane); }

@@ -50,6 +50,7 @@ struct Grid {
   int nx, ny, pitch;
   long long ps;           // plane stride in elements
   int psi;                // the same as int (9 * ps < 2^31 is validated)
+  int fast;               // 36 * ps < 2^32: byte offsets into a 9-plane FP32 array fit 32 bits
 };
 
 struct StepArgs {

@@ -79,10 +79,42 @@ __device__ __forceinline__ float pull(const float* __restrict__ base, int x, int
   return base[(unsigned)(sl * g.psi + o)];
 }
 
+// Interior tiles (every pull and every halo position inside the domain)
+// address memory as one uniform base pointer per array plus a 32-bit
+// per-thread byte offset (the SGPR-base global load/store forms).  The plane
+// index and the source shift of a pulled population are one uniform term
+// added to the node's byte offset: the f and h pulls of a direction share
+// that offset, so an access costs at most one 32-bit vector add.
+template <class T>
+__device__ __forceinline__ T ldb(const T* base, unsigned off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+}
+template <class T>
+__device__ __forceinline__ void stb(T* base, unsigned off, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off) = v;
+}
+// Byte offset, within a 9-plane FP32 array, of population I pulled by the
+// node at byte offset ob: plane I at the node x - c_I.  Below 2^32 when
+// Grid::fast is set (36 ps < 2^32); the arithmetic is modulo 2^32.
+template <int I>
+__device__ __forceinline__ unsigned pull_off(const Grid& g, unsigned ob) {
+  return ob + 4u * (unsigned)I * (unsigned)g.psi - 4u * (unsigned)(cx(I) + cy(I) * g.pitch);
+}
+// Byte offset of the node x - c_I in a single plane (x - c_I is inside the
+// domain for an interior tile, so the difference is non-negative).
+template <int I>
+__device__ __forceinline__ unsigned src_off_b(const Grid& g, unsigned ob) {
+  return ob - 4u * (unsigned)(cx(I) + cy(I) * g.pitch);
+}
+template <int I>
+__device__ __forceinline__ float pull_fast(const float* planes, const Grid& g, unsigned ob) {
+  return ldb(planes, pull_off<I>(g, ob));
+}
+
 // 1/x in FP64 from an FP32 seed and two Newton steps (exact to ~1 ulp for
 // the positive, normal arguments used here: densities, relaxation times).
 __device__ __forceinline__ double rcp64(double x) {
-  double r = (double)__frcp_rn((float)x);
+  double r = (double)__builtin_amdgcn_rcpf((float)x);   // ~1 ulp FP32 seed
   r = r * (2.0 - x * r);
   r = r * (2.0 - x * r);
   return r;
@@ -345,10 +377,82 @@ __device__ __forceinline__ bool xcd_tile(int ntx, int nty, int& tx, int& ty) {
   return true;
 }
 
+// c_i . v with the zero components of c_i dropped once the direction loop is
+// unrolled (x + (-0.0) folds to x; 0 * x does not fold).
+__device__ __forceinline__ double dotc(int i, double vx, double vy) {
+  const double tx = cx(i) == 0 ? -0.0 : (cx(i) > 0 ? vx : -vx);
+  const double ty = cy(i) == 0 ? -0.0 : (cy(i) > 0 ? vy : -vy);
+  return tx + ty;
+}
+__device__ __forceinline__ float dotcf(int i, float vx, float vy) {
+  const float tx = cx(i) == 0 ? -0.0f : (cx(i) > 0 ? vx : -vx);
+  const float ty = cy(i) == 0 ? -0.0f : (cy(i) > 0 ? vy : -vy);
+  return tx + ty;
+}
+
+// Pulled flow populations and source pressures of a node of an interior tile.
+__device__ __forceinline__ void load_fp_fast(const StepArgs& a, unsigned ob, float* ft, float* ps) {
+#define PULL_FP_FAST(I)                         \
+  ft[I] = pull_fast<I>(a.fin, a.g, ob);         \
+  ps[I] = ldb(a.pin, src_off_b<I>(a.g, ob));
+  PULL_FP_FAST(0) PULL_FP_FAST(1) PULL_FP_FAST(2) PULL_FP_FAST(3) PULL_FP_FAST(4)
+  PULL_FP_FAST(5) PULL_FP_FAST(6) PULL_FP_FAST(7) PULL_FP_FAST(8)
+#undef PULL_FP_FAST
+}
+
+// A tile is interior when every position it reads (the phi halo reaches 3
+// nodes past the tile) lies inside the domain: no wrap, mirror or bounce;
+// its 32-bit byte offsets need Grid::fast.
+__device__ __forceinline__ bool interior_tile(int x0, int y0, const Grid& g) {
+  return g.fast && x0 >= 3 && y0 >= 3 && x0 + kTX + 3 <= g.nx && y0 + kTY + 3 <= g.ny;
+}
+
+// Wall term of Eq. (43) for a population leaving node (x, y) in direction
+// I: true (and c_i . u_w) when x + c_i lies beyond a wall.
+template <int I, bool WX, bool WY>
+__device__ __forceinline__ bool wall_hit(int x, int y, const Grid& g, const Phys& c, double& cuw) {
+  const int tx = x + cx(I), tyy = y + cy(I);
+  bool hit = false;
+  cuw = 0.0;
+  if (WX && cx(I) != 0 && (tx < 0 || tx >= g.nx)) { hit = true; cuw = (double)cy(I) * (tx < 0 ? c.uw_lo_d : c.uw_hi_d); }
+  if (WY && cy(I) != 0 && (tyy < 0 || tyy >= g.ny)) { hit = true; cuw = (double)cx(I) * (tyy < 0 ? c.uw_lo_d : c.uw_hi_d); }
+  return hit;
+}
+
+// Collision results of one opposite pair (I, J = opp(I)) of both population
+// sets, stored with the wall term applied (general tiles) or directly
+// (interior tiles).
+template <int I, bool FAST, bool WX, bool WY>
+__device__ __forceinline__ void store_pair(const StepArgs& a, int x, int y, unsigned o, unsigned ob, double fpi,
+                                           double fpj, double hpi, double hpj, double rho, double phid,
+                                           double& d0sum) {
+  constexpr int J = opp(I);
+  if constexpr (!FAST) {
+    double cuw;
+    if (wall_hit<I, WX, WY>(x, y, a.g, a.c, cuw)) { fpi -= 2.0 * wtd(I) * rho * cuw; hpi -= 6.0 * wtd(I) * phid * cuw; }
+    if (wall_hit<J, WX, WY>(x, y, a.g, a.c, cuw)) { fpj -= 2.0 * wtd(J) * rho * cuw; hpj -= 6.0 * wtd(J) * phid * cuw; }
+  }
+  const float hsi = (float)hpi, hsj = (float)hpj;
+  d0sum += (double)hsi + (double)hsj;
+  if constexpr (FAST) {
+    const unsigned oi = ob + 4u * (unsigned)I * (unsigned)a.g.psi, oj = ob + 4u * (unsigned)J * (unsigned)a.g.psi;
+    stb(a.fout, oi, (float)fpi);
+    stb(a.fout, oj, (float)fpj);
+    stb(a.hout, oi, hsi);
+    stb(a.hout, oj, hsj);
+  } else {
+    a.fout[(unsigned)(I * a.g.psi) + o] = (float)fpi;
+    a.fout[(unsigned)(J * a.g.psi) + o] = (float)fpj;
+    a.hout[(unsigned)(I * a.g.psi) + o] = hsi;
+    a.hout[(unsigned)(J * a.g.psi) + o] = hsj;
+  }
+}
+
 // One 64x8 tile of the step (or of the moments): the whole per-node update
-// of a1-a12.  Called by the single-lattice kernel and the batched kernel.
-template <int FORM, bool MOMENTS, int BC>
-__device__ __forceinline__ void fused_tile(Lds& s, const StepArgs& a, const MomentArgs& m, int tile_x, int tile_y) {
+// of a1-a12.  FAST: an interior tile (see interior_tile), step only.
+template <int FORM, bool MOMENTS, int BC, bool FAST>
+__device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const MomentArgs& m, int tile_x, int tile_y) {
+  static_assert(!(FAST && MOMENTS), "the moments use the general path");
   constexpr bool WX = (BC & 1) != 0, WY = (BC & 2) != 0;   // walled axes (compile time)
   const int tid = threadIdx.x;
   const int x0 = tile_x * kTX, y0 = tile_y * kTY;
@@ -357,8 +461,17 @@ __device__ __forceinline__ void fused_tile(Lds& s, const StepArgs& a, const Mome
   const Phys& c = a.c;
   const int uy_ = ty + 1, ux_ = lx + 1;             // velocity-ring coordinates of this node
   int x, y;
-  const bool valid = ring_global<WX, WY>(uy_, ux_, x0, y0, a, x, y);
-  const bool act = (x0 + lx < g.nx) && (y0 + ty < g.ny);
+  bool valid, act;
+  if constexpr (FAST) {
+    x = x0 + lx;
+    y = y0 + ty;
+    valid = act = true;
+  } else {
+    valid = ring_global<WX, WY>(uy_, ux_, x0, y0, a, x, y);
+    act = (x0 + lx < g.nx) && (y0 + ty < g.ny);
+  }
+  const unsigned o = (unsigned)(y * g.pitch + x);   // node offset (valid nodes)
+  const unsigned ob = o * 4u;                       // its byte offset in an FP32 plane
 
   // This node's flow populations are pulled after the ring velocities (the
   // ring threads would otherwise hold both sets of registers at once).
@@ -367,9 +480,13 @@ __device__ __forceinline__ void fused_tile(Lds& s, const StepArgs& a, const Mome
   // Stage A: phi tile with a 3-node halo (periodic wrap / even reflection at walls, Sec. IV)
   for (int k = tid; k < PH * PW; k += kFusedThreads) {
     const int py = k / PW, px = k - py * PW;
-    const int gx = halo_coord<WX>(x0 + px - 3, g.nx);
-    const int gy = halo_coord<WY>(y0 + py - 3, g.ny);
-    s.phi[py][px] = a.phi[(unsigned)(gy * g.pitch + gx)];
+    if constexpr (FAST) {
+      s.phi[py][px] = ldb(a.phi, (unsigned)((y0 + py - 3) * g.pitch + (x0 + px - 3)) * 8u);   // < 8 ps < 2^32
+    } else {
+      const int gx = halo_coord<WX>(x0 + px - 3, g.nx);
+      const int gy = halo_coord<WY>(y0 + py - 3, g.ny);
+      s.phi[py][px] = a.phi[(unsigned)(gy * g.pitch + gx)];
+    }
   }
   __syncthreads();
 
@@ -379,11 +496,18 @@ __device__ __forceinline__ void fused_tile(Lds& s, const StepArgs& a, const Mome
   // Stage C: velocities of the ring (step only), then of this node.
   if constexpr (!MOMENTS) {
     if (tid < NRING) {
-      int ruy, rux, rx, ry;
+      int ruy, rux;
       ring_pos(tid, ruy, rux);
-      if (ring_global<WX, WY>(ruy, rux, x0, y0, a, rx, ry)) {
-        float rft[9], rps[9];
-        load_fp<WX, WY>(a, rx, ry, rft, rps);
+      float rft[9], rps[9];
+      bool ok = true;
+      if constexpr (FAST) {
+        load_fp_fast(a, (unsigned)((y0 + ruy - 1) * g.pitch + (x0 + rux - 1)) * 4u, rft, rps);
+      } else {
+        int rx, ry;
+        ok = ring_global<WX, WY>(ruy, rux, x0, y0, a, rx, ry);
+        if (ok) load_fp<WX, WY>(a, rx, ry, rft, rps);
+      }
+      if (ok) {
         NodeState rs;
         velocity_from<FORM, false>(s, a, ruy, rux, rft, rps, rs);
         const double ph = s.phi[ruy + 2][rux + 2];
@@ -394,7 +518,8 @@ __device__ __forceinline__ void fused_tile(Lds& s, const StepArgs& a, const Mome
   }
   NodeState n;
   if (valid) {
-    load_fp<WX, WY>(a, x, y, ft, ps);
+    if constexpr (FAST) load_fp_fast(a, ob, ft, ps);
+    else load_fp<WX, WY>(a, x, y, ft, ps);
     velocity_from<FORM, true>(s, a, uy_, ux_, ft, ps, n);
     if constexpr (!MOMENTS) {
       const double ph = s.phi[uy_ + 2][ux_ + 2];
@@ -404,17 +529,43 @@ __device__ __forceinline__ void fused_tile(Lds& s, const StepArgs& a, const Mome
   }
   if constexpr (MOMENTS) {
     if (act) {
-      const long long o = (long long)y * g.nx + x;
-      if (m.phi) m.phi[o] = (float)s.phi[ty + 3][lx + 3];
-      if (m.rho) m.rho[o] = (float)n.rho;
-      if (m.ux) m.ux[o] = (float)n.ux;
-      if (m.uy) m.uy[o] = (float)n.uy;
-      if (m.p) m.p[o] = (float)n.P;
+      const long long om = (long long)y * g.nx + x;
+      if (m.phi) m.phi[om] = (float)s.phi[ty + 3][lx + 3];
+      if (m.rho) m.rho[om] = (float)n.rho;
+      if (m.ux) m.ux[om] = (float)n.ux;
+      if (m.uy) m.uy[om] = (float)n.uy;
+      if (m.p) m.p[om] = (float)n.P;
     }
     return;
   } else {
     __syncthreads();
     if (!act) return;
+    {
+      if constexpr (FAST) {
+        h[1] = pull_fast<1>(a.hin, g, ob);
+        h[2] = pull_fast<2>(a.hin, g, ob);
+        h[3] = pull_fast<3>(a.hin, g, ob);
+        h[4] = pull_fast<4>(a.hin, g, ob);
+        h[5] = pull_fast<5>(a.hin, g, ob);
+        h[6] = pull_fast<6>(a.hin, g, ob);
+        h[7] = pull_fast<7>(a.hin, g, ob);
+        h[8] = pull_fast<8>(a.hin, g, ob);
+        j0 = ldb((const float*)a.J, ob);
+        j1 = ldb((const float*)a.J, ob + 4u * (unsigned)g.psi);
+      } else {
+        constexpr int wx = WX, wy = WY;
+        h[1] = pull<1>(a.hin, x, y, g, wx, wy);
+        h[2] = pull<2>(a.hin, x, y, g, wx, wy);
+        h[3] = pull<3>(a.hin, x, y, g, wx, wy);
+        h[4] = pull<4>(a.hin, x, y, g, wx, wy);
+        h[5] = pull<5>(a.hin, x, y, g, wx, wy);
+        h[6] = pull<6>(a.hin, x, y, g, wx, wy);
+        h[7] = pull<7>(a.hin, x, y, g, wx, wy);
+        h[8] = pull<8>(a.hin, x, y, g, wx, wy);
+        j0 = a.J[o];
+        j1 = a.J[(unsigned)g.psi + o];
+      }
+    }
 
     const int py = uy_ + 2, px = ux_ + 2;
     const double phid = s.phi[py][px];
@@ -425,40 +576,38 @@ __device__ __forceinline__ void fused_tile(Lds& s, const StepArgs& a, const Mome
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
       int qy = uy_ + cy(i), qx = ux_ + cx(i);
-      const int nxg = x + cx(i), nyg = y + cy(i);
-      const bool gx_ = WX && (nxg < 0 || nxg >= g.nx);
-      const bool gy_ = WY && (nyg < 0 || nyg >= g.ny);
-      if (gx_) qx = ux_;
-      if (gy_) qy = uy_;
-      float vx = s.q[0][qy][qx], vy = s.q[1][qy][qx];
-      if (gx_ || gy_) {
-        const float phm = (float)s.phi[qy + 2][qx + 2];
-        if (gx_) { vx = -vx; vy = 2.f * (nxg < 0 ? c.uw_lo : c.uw_hi) * phm - vy; }
-        if (gy_) { vx = 2.f * (nyg < 0 ? c.uw_lo : c.uw_hi) * phm - vx; vy = -vy; }
+      float vx, vy;
+      if constexpr (FAST) {
+        vx = s.q[0][qy][qx];
+        vy = s.q[1][qy][qx];
+      } else {
+        const int nxg = x + cx(i), nyg = y + cy(i);
+        const bool gx_ = WX && (nxg < 0 || nxg >= g.nx);
+        const bool gy_ = WY && (nyg < 0 || nyg >= g.ny);
+        if (gx_) qx = ux_;
+        if (gy_) qy = uy_;
+        vx = s.q[0][qy][qx];
+        vy = s.q[1][qy][qx];
+        if (gx_ || gy_) {
+          const float phm = (float)s.phi[qy + 2][qx + 2];
+          if (gx_) { vx = -vx; vy = 2.f * (nxg < 0 ? c.uw_lo : c.uw_hi) * phm - vy; }
+          if (gy_) { vx = 2.f * (nyg < 0 ? c.uw_lo : c.uw_hi) * phm - vx; vy = -vy; }
+        }
       }
-      dqf += wt(i) * ((float)cx(i) * vx + (float)cy(i) * vy);
+      dqf += wt(i) * dotcf(i, vx, vy);
     }
     const double dq = 3.0 * (double)dqf;
-    {
-      constexpr int wx = WX, wy = WY;
-      h[1] = pull<1>(a.hin, x, y, g, wx, wy);
-      h[2] = pull<2>(a.hin, x, y, g, wx, wy);
-      h[3] = pull<3>(a.hin, x, y, g, wx, wy);
-      h[4] = pull<4>(a.hin, x, y, g, wx, wy);
-      h[5] = pull<5>(a.hin, x, y, g, wx, wy);
-      h[6] = pull<6>(a.hin, x, y, g, wx, wy);
-      h[7] = pull<7>(a.hin, x, y, g, wx, wy);
-      h[8] = pull<8>(a.hin, x, y, g, wx, wy);
-      const int oj = y * g.pitch + x;
-      j0 = a.J[(unsigned)oj];
-      j1 = a.J[(unsigned)(g.psi + oj)];
-    }
-    const int o = y * g.pitch + x;
     const double qx = phid * n.ux, qy = phid * n.uy;
     const double dtx = qx - (double)j0, dty = qy - (double)j1;   // explicit-Euler d_t(phi u) (A4)
-    a.J[(unsigned)o] = (float)qx;
-    a.J[(unsigned)(g.psi + o)] = (float)qy;
-    a.pout[(unsigned)o] = n.Pn;
+    if constexpr (FAST) {
+      stb(a.J, ob, (float)qx);
+      stb(a.J, ob + 4u * (unsigned)g.psi, (float)qy);
+      stb(a.pout, ob, n.Pn);
+    } else {
+      a.J[o] = (float)qx;
+      a.J[(unsigned)g.psi + o] = (float)qy;
+      a.pout[o] = n.Pn;
+    }
 
     if (!(isfinite(n.ux) && isfinite(n.uy) && isfinite(phid))) atomicOr(a.status, 1);
 
@@ -474,27 +623,6 @@ __device__ __forceinline__ void fused_tile(Lds& s, const StepArgs& a, const Mome
     const double G0 = omh * c.eta_d * (double)n.mu + cfh * (c.a_h_d * dq);
     const double Vx = omh * qx + cfh * dtx, Vy = omh * qy + cfh * dty;
     const double keep_h = 1.0 - omh;
-    double d0sum = 0.0;   // sum of the stored h_i^+ (i >= 1)
-#pragma unroll
-    for (int i = 1; i < 9; ++i) {
-      const double cV = (cx(i) != 0 ? cx(i) * Vx : 0.0) + (cy(i) != 0 ? cy(i) * Vy : 0.0);
-      double hp = keep_h * (double)h[i] + wtd(i) * (G0 + 3.0 * cV);
-      // Eq. (43): a population about to cross a wall is stored in its own
-      // slot with the moving-wall term; the next pull reads it as opp(i).
-      const int tx = x + cx(i), tyy = y + cy(i);
-      double cuw = 0.0;
-      bool hit = false;
-      if (WX && (tx < 0 || tx >= g.nx)) { hit = true; cuw = (double)cy(i) * (tx < 0 ? c.uw_lo_d : c.uw_hi_d); }
-      if (WY && (tyy < 0 || tyy >= g.ny)) { hit = true; cuw = (double)cx(i) * (tyy < 0 ? c.uw_lo_d : c.uw_hi_d); }
-      if (hit) hp -= 6.0 * wtd(i) * phid * cuw;
-      const float hs = (float)hp;
-      d0sum += (double)hs;
-      a.hout[(unsigned)(i * g.psi + o)] = hs;
-    }
-    // slot 0 holds d0 = h_0^+ - phi.  The collision conserves sum_i h_i = phi
-    // (Eqs. 32 and 36), so d0 = -sum_{i>=1} h_i^+ exactly; forming it from
-    // the stored values makes the update of phi conservative.
-    a.hout[(unsigned)o] = (float)(-d0sum);
 
     // Flow collision, Eq. (29) with f^eq of Eq. (31) and F_i of Eq. (35)
     // (reading A1), factored per node.  With s_i = 3 c.u + 4.5 (c.u)^2 - 1.5 u^2,
@@ -503,30 +631,58 @@ __device__ __forceinline__ void fused_tile(Lds& s, const StepArgs& a, const Mome
     //        + w_i [K0 + k c.F + s_i (K1 + k c.F + k c.grad(rho)/3)],
     //   k = 1 - 1/(2 tau_f), K0 = (P - Pn)/tau_f - k u.F,
     //   K1 = rho/(3 tau_f) - k u.F - k u.grad(rho)/3.
+    // Directions come in opposite pairs (c_J = -c_I): s = e +- o with the
+    // even part e = 4.5 (c.u)^2 - 1.5 u^2 and the odd part o = 3 c.u, so
+    // f_I^+, f_J^+ = keep f + w (S +- Q) with S = K0 + e K1 + o d,
+    // Q = c.kF + e d + o K1, d = c.kF + c.kG.  Likewise h_I^+, h_J^+ =
+    // keep h + w (G0 +- 3 c.V).
     const double fx = (double)n.fx, fy = (double)n.fy, grx = (double)n.grx, gry = (double)n.gry;
     const double uF = n.ux * fx + n.uy * fy, uG = n.ux * grx + n.uy * gry;
     const double K0 = omf * (n.P - (double)n.Pn) - cff * uF;
     const double K1 = omf * n.rho * (1.0 / 3.0) - cff * uF - cff * uG * (1.0 / 3.0);
-    const double kFx = cff * fx, kFy = cff * fy, kGx = cff * grx * (1.0 / 3.0), kGy = cff * gry * (1.0 / 3.0);
+    const double kFx = cff * fx, kFy = cff * fy;
+    const double kFGx = kFx + cff * grx * (1.0 / 3.0), kFGy = kFy + cff * gry * (1.0 / 3.0);
     const double keep_f = 1.0 - omf, m15usq = -1.5 * usq;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      const double cu = (cx(i) != 0 ? cx(i) * n.ux : 0.0) + (cy(i) != 0 ? cy(i) * n.uy : 0.0);
-      const double si = fma(fma(4.5, cu, 3.0), cu, m15usq);        // s_i(u), Eq. (33)
-      const double cF = (cx(i) != 0 ? cx(i) * kFx : 0.0) + (cy(i) != 0 ? cy(i) * kFy : 0.0);
-      const double cG = (cx(i) != 0 ? cx(i) * kGx : 0.0) + (cy(i) != 0 ? cy(i) * kGy : 0.0);
-      double fp = keep_f * (double)n.f[i] + wtd(i) * (K0 + cF + si * (K1 + cF + cG));
-      if (i != 0) {
-        const int tx = x + cx(i), tyy = y + cy(i);
-        double cuw = 0.0;
-        bool hit = false;
-        if (WX && (tx < 0 || tx >= g.nx)) { hit = true; cuw = (double)cy(i) * (tx < 0 ? c.uw_lo_d : c.uw_hi_d); }
-        if (WY && (tyy < 0 || tyy >= g.ny)) { hit = true; cuw = (double)cx(i) * (tyy < 0 ? c.uw_lo_d : c.uw_hi_d); }
-        if (hit) fp -= 2.0 * wtd(i) * n.rho * cuw;
-      }
-      a.fout[(unsigned)(i * g.psi + o)] = (float)fp;
+    double d0sum = 0.0;   // sum of the stored h_i^+ (i >= 1)
+    {
+      const double fp0 = keep_f * (double)n.f[0] + wtd(0) * fma(m15usq, K1, K0);
+      if constexpr (FAST) stb(a.fout, ob, (float)fp0);
+      else a.fout[o] = (float)fp0;
+    }
+#define COLLIDE_PAIR(I)                                                                        \
+  {                                                                                            \
+    constexpr int J_ = opp(I);                                                                 \
+    const double cu = dotc(I, n.ux, n.uy);                                                     \
+    const double e = fma(4.5 * cu, cu, m15usq), od = 3.0 * cu;                                 \
+    const double cF = dotc(I, kFx, kFy), d = dotc(I, kFGx, kFGy);                              \
+    const double S = fma(od, d, fma(e, K1, K0)), Q = fma(od, K1, fma(e, d, cF));               \
+    const double wS = wtd(I) * S, wQ = wtd(I) * Q;                                             \
+    const double fpi = fma(keep_f, (double)n.f[I], wS + wQ);                                   \
+    const double fpj = fma(keep_f, (double)n.f[J_], wS - wQ);                                  \
+    const double wG = wtd(I) * G0, t = (3.0 * wtd(I)) * dotc(I, Vx, Vy);                      \
+    const double hpi = fma(keep_h, (double)h[I], wG + t);                                      \
+    const double hpj = fma(keep_h, (double)h[J_], wG - t);                                     \
+    store_pair<I, FAST, WX, WY>(a, x, y, o, ob, fpi, fpj, hpi, hpj, n.rho, phid, d0sum);       \
+  }
+    COLLIDE_PAIR(1) COLLIDE_PAIR(2) COLLIDE_PAIR(5) COLLIDE_PAIR(6)
+#undef COLLIDE_PAIR
+    // slot 0 holds d0 = h_0^+ - phi.  The collision conserves sum_i h_i = phi
+    // (Eqs. 32 and 36), so d0 = -sum_{i>=1} h_i^+ exactly; forming it from
+    // the stored values makes the update of phi conservative.
+    if constexpr (FAST) stb(a.hout, ob, (float)(-d0sum));
+    else a.hout[o] = (float)(-d0sum);
+  }
+}
+
+template <int FORM, bool MOMENTS, int BC>
+__device__ __forceinline__ void fused_tile(Lds& s, const StepArgs& a, const MomentArgs& m, int tile_x, int tile_y) {
+  if constexpr (!MOMENTS) {
+    if (interior_tile(tile_x * kTX, tile_y * kTY, a.g)) {
+      tile_impl<FORM, false, BC, true>(s, a, m, tile_x, tile_y);
+      return;
     }
   }
+  tile_impl<FORM, MOMENTS, BC, false>(s, a, m, tile_x, tile_y);
 }
 
 template <int FORM, bool MOMENTS, int BC>

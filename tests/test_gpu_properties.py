@@ -126,3 +126,38 @@ def test_full_size_channel_one_step():
     """1024x4096 bubble between x-walls with gravity."""
     p, phi0, _, _ = WL.config_bubble()
     _one_step_full_size(p, phi0, "stf2")
+
+
+@pytest.mark.parametrize("case", ["periodic_stf1", "ywalls_csf2", "xwalls_gravity_pf2"])
+def test_interior_fast_path_bitwise_equals_general_path(case, monkeypatch):
+    """Tiles away from the edges take the interior addressing path; with
+    PFLBM_GENERAL_PATH=1 every tile takes the general one.  Same arithmetic,
+    so the saved states must agree bit for bit."""
+    import paper_2012_14729_amd as P
+    nx, ny = 320, 96
+    if case == "periodic_stf1":
+        p = WL.ParamSet(nx=nx, ny=ny, rho1=10.0, rho2=1.0, nu1=0.1, nu2=0.2, sigma=5e-3, W=4.0, M=0.1, tau_h=0.8)
+        phi0, ux0, uy0, form = WL.two_droplets(nx, ny, 20.0, 14.0, 2.0, 4.0), None, None, "stf1"
+    elif case == "ywalls_csf2":
+        p, phi0, ux0, uy0 = WL.config_shear(nx=nx, ny=ny, R=20.0, Re=1.0, Ca=0.2)
+        form = "csf2"
+    else:
+        p = WL.ParamSet(nx=nx, ny=ny, wall_x=1, rho1=1.0, rho2=0.1, nu1=0.1, nu2=0.1, sigma=1e-3, W=4.0, M=0.1,
+                        tau_h=0.8, gy=-2e-5)
+        phi0, ux0, uy0, form = WL.droplet(nx, ny, 18.0, 4.0, xc=150.0, yc=40.0, inside=-1.0), None, None, "pf2"
+    phi0 = np.asarray(phi0, np.float32)
+    blobs = []
+    for general in (False, True):
+        if general:
+            monkeypatch.setenv("PFLBM_GENERAL_PATH", "1")
+        else:
+            monkeypatch.delenv("PFLBM_GENERAL_PATH", raising=False)
+        sim = P.Simulation(p.as_dict(), phi0, ux0, uy0)
+        sim.step(40, form)
+        blobs.append(sim.save().cpu())
+        assert not sim.status()
+    monkeypatch.delenv("PFLBM_GENERAL_PATH", raising=False)
+    a, b = blobs[0].numpy(), blobs[1].numpy()
+    nd = int((a != b).sum())
+    print(f"[fast-vs-general] {case}: {nd} differing bytes of {a.size}", flush=True)
+    assert nd == 0
