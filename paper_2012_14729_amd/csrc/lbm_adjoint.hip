@@ -35,8 +35,7 @@ constexpr double CS2 = 1.0 / 3.0;
 
 struct AGrid {
   int nx, ny, wx, wy;
-  int pitch;        // pitch of the single-lattice state planes
-  long long ps;     // plane stride of the state planes
+  Grid sg;          // layout of the simulation's state arrays
 };
 
 __device__ __forceinline__ int i0(const AGrid& g, int x, int y) { return y * g.nx + x; }
@@ -97,9 +96,7 @@ struct ACon {
 // Physical pre-collision state from the stored single-lattice state (pull
 // form of streaming, Eq. 43 pre-applied): f_i = ft_i + w_i P at the source,
 // h_i pulled for i >= 1, h_0 = phi - sum_{i>=1} h_i, J.
-__global__ void k_adj_unpack(const float* __restrict__ fs, const float* __restrict__ Ps,
-                             const float* __restrict__ hs, const float* __restrict__ Js,
-                             const double* __restrict__ phis, AGrid g, ABuf b) {
+__global__ void k_adj_unpack(const float* __restrict__ S, const double* __restrict__ phis, AGrid g, ABuf b) {
   const int k = blockIdx.x * kB + threadIdx.x;
   if (k >= g.nx * g.ny) return;
   const int x = k % g.nx, y = k / g.nx;
@@ -110,19 +107,19 @@ __global__ void k_adj_unpack(const float* __restrict__ fs, const float* __restri
     bool bounce = false;
     if (sx < 0 || sx >= g.nx) { if (g.wx) bounce = true; else sx = (sx + g.nx) % g.nx; }
     if (sy < 0 || sy >= g.ny) { if (g.wy) bounce = true; else sy = (sy + g.ny) % g.ny; }
-    long long o = bounce ? (long long)y * g.pitch + x : (long long)sy * g.pitch + sx;
+    const unsigned nb = bounce ? nbase(g.sg, x, y) : nbase(g.sg, sx, sy);
     if (bounce) slot = opp(i);
-    b.f[(size_t)i * N + k] = (double)fs[slot * g.ps + o] + wtd(i) * (double)Ps[o];
+    b.f[(size_t)i * N + k] = (double)S[nb + (unsigned)((kPF + slot) * 64)] + wtd(i) * (double)S[nb + (unsigned)(kPP * 64)];
     if (i > 0) {
-      const double hv = (double)hs[slot * g.ps + o];
+      const double hv = (double)S[nb + (unsigned)((kPH + slot) * 64)];
       b.h[(size_t)i * N + k] = hv;
       hsum += hv;
     }
   }
-  const long long o = (long long)y * g.pitch + x;
-  b.h[k] = phis[o] - hsum;
-  b.J[k] = (double)Js[o];
-  b.J[N + k] = (double)Js[g.ps + o];
+  const unsigned on = nbase(g.sg, x, y);
+  b.h[k] = phis[(long long)y * g.sg.pitch + x] - hsum;
+  b.J[k] = (double)S[on + (unsigned)(kPJ * 64)];
+  b.J[N + k] = (double)S[on + (unsigned)((kPJ + 1) * 64)];
 }
 
 __global__ void k_adj_fa(AGrid g, ABuf b) {   // phi = sum_i h_i (Eq. 37), then the e2 extension
@@ -758,7 +755,11 @@ int lbm_adjoint_create(lbm_adj** out, lbm_sim* sim, void* d_ws, size_t ws_bytes)
   a->ws = (char*)d_ws;
   const int nx = p.nx, ny = p.ny;
   a->g.nx = nx; a->g.ny = ny; a->g.wx = p.wall_x; a->g.wy = p.wall_y;
-  sim_grid(sim, &a->g.pitch, &a->g.ps);
+  {
+    SimView v;
+    if (int r = sim_view(sim, &v)) { delete a; return r; }
+    a->g.sg = v.g;
+  }
   const Phys ph = sim_phys(sim);
   ACon& c = a->c;
   c.beta4 = ph.beta4_d; c.kappa = ph.kappa_d; c.sigma = p.sigma; c.eps2 = ph.eps2_d;
@@ -802,7 +803,7 @@ int lbm_adjoint_seed_phi_misfit(lbm_adj* a, const float* d_target, double* d_lam
   const size_t N = (size_t)a->p.nx * a->p.ny;
   SimView v;
   if (int r = sim_view(a->sim, &v)) return r;
-  hipLaunchKernelGGL(k_adj_unpack, dim3(nblk(N)), dim3(kB), 0, st, v.f, v.P, v.h, v.J, v.phi, a->g, a->b);
+  hipLaunchKernelGGL(k_adj_unpack, dim3(nblk(N)), dim3(kB), 0, st, v.s, v.phi, a->g, a->b);
   hipLaunchKernelGGL(k_adj_fa, dim3(nblk((a->p.nx + 4) * (a->p.ny + 4))), dim3(kB), 0, st, a->g, a->b);
   hipLaunchKernelGGL(k_adj_seed, dim3(nblk(N)), dim3(kB), 0, st, a->g, a->b.phi, d_target, d_lambda, a->lossd);
   hipLaunchKernelGGL(k_adj_sum, dim3(1), dim3(kB), 0, st, a->lossd, (long long)N, a->red + 2);
@@ -824,7 +825,7 @@ int lbm_adjoint_step(lbm_adj* a, int32_t form, double* d_lambda, void* stream) {
                   N2 = (long long)(g.nx + 4) * (g.ny + 4);
   SimView v;
   if (int r = sim_view(a->sim, &v)) return r;
-  hipLaunchKernelGGL(k_adj_unpack, dim3(nblk(N)), dim3(kB), 0, st, v.f, v.P, v.h, v.J, v.phi, g, a->b);
+  hipLaunchKernelGGL(k_adj_unpack, dim3(nblk(N)), dim3(kB), 0, st, v.s, v.phi, g, a->b);
   hipLaunchKernelGGL(k_adj_fa, dim3(nblk(N2)), dim3(kB), 0, st, g, a->b);
   hipLaunchKernelGGL(k_adj_fb, dim3(nblk(N1)), dim3(kB), 0, st, g, a->c, a->b);
   hipLaunchKernelGGL(k_adj_fc, dim3(nblk(N)), dim3(kB), 0, st, g, a->c, a->b);

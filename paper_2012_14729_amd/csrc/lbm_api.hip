@@ -51,8 +51,8 @@ bool finite(double v) { return std::isfinite(v); }
 int validate(const lbm_params* p) {
   if (!p) return fail(LBM_E_INVAL, "params is NULL");
   if (p->nx < 8 || p->ny < 8) return fail(LBM_E_INVAL, "nx, ny must be >= 8 (got %d, %d)", p->nx, p->ny);
-  if (9LL * (((long long)p->nx + 63) / 64 * 64) * p->ny >= (1LL << 31))
-    return fail(LBM_E_INVAL, "grid too large (9 planes must hold fewer than 2^31 elements)");
+  if (21LL * (((long long)p->nx + 63) / 64 * 64) * p->ny >= (1LL << 32))
+    return fail(LBM_E_INVAL, "grid too large (a 21-plane state array must hold fewer than 2^32 elements)");
   if ((p->wall_x != 0 && p->wall_x != 1) || (p->wall_y != 0 && p->wall_y != 1))
     return fail(LBM_E_INVAL, "wall_x, wall_y must be 0 or 1");
   if (p->wall_x && p->wall_y && (p->u_wall_lo != 0.0 || p->u_wall_hi != 0.0))
@@ -124,7 +124,7 @@ Phys derive(const lbm_params* p, double rho0) { return derive_phys(p, rho0); }
 
 struct Layout {
   Grid g;
-  size_t off_f[2], off_h[2], off_P[2], off_J, off_phi, off_status, off_partial, off_sum, total;
+  size_t off_s[2], off_phi, off_status, off_partial, off_sum, total;
 };
 
 constexpr int kPartials = 512;
@@ -134,17 +134,15 @@ Layout layout_for(const lbm_params* p) {
   L.g.nx = p->nx;
   L.g.ny = p->ny;
   L.g.pitch = (int)align_up((size_t)p->nx, 64);
+  L.g.ncx = L.g.pitch / 64;
   L.g.ps = (long long)L.g.pitch * p->ny;
-  L.g.psi = (int)L.g.ps;
-  L.g.fast = 36LL * L.g.ps < (1LL << 32) ? 1 : 0;
+  L.g.rowe = L.g.ncx * kSegE;
+  L.g.fast = 1;
   if (const char* e = std::getenv("PFLBM_GENERAL_PATH"))   // diagnostics: every tile on the general path
     if (e[0] == '1') L.g.fast = 0;
-  const size_t plane = (size_t)L.g.ps * sizeof(float);
+  const size_t sbytes = (size_t)kNPL * (size_t)L.g.ps * sizeof(float);
   size_t o = 0;
-  for (int b = 0; b < 2; ++b) { L.off_f[b] = o; o = align_up(o + 9 * plane, kAlign); }
-  for (int b = 0; b < 2; ++b) { L.off_h[b] = o; o = align_up(o + 9 * plane, kAlign); }
-  for (int b = 0; b < 2; ++b) { L.off_P[b] = o; o = align_up(o + plane, kAlign); }
-  L.off_J = o; o = align_up(o + 2 * plane, kAlign);
+  for (int b = 0; b < 2; ++b) { L.off_s[b] = o; o = align_up(o + sbytes, kAlign); }
   L.off_phi = o; o = align_up(o + (size_t)L.g.ps * sizeof(double), kAlign);
   L.off_status = o; o = align_up(o + 64 * sizeof(int), kAlign);
   L.off_partial = o; o = align_up(o + kPartials * sizeof(double), kAlign);
@@ -171,11 +169,9 @@ struct lbm_sim {
   int ev_next[2];
   double t_ms[2];
   int64_t t_n[2];
-  float* f(int b) const { return (float*)(ws + L.off_f[b]); }
-  float* h(int b) const { return (float*)(ws + L.off_h[b]); }
-  float* P(int b) const { return (float*)(ws + L.off_P[b]); }
-  float* J() const { return (float*)(ws + L.off_J); }
+  float* S(int b) const { return (float*)(ws + L.off_s[b]); }
   double* phi() const { return (double*)(ws + L.off_phi); }
+  size_t state_floats() const { return (size_t)kNPL * (size_t)L.g.ps; }
   int* status() const { return (int*)(ws + L.off_status); }
 };
 
@@ -183,13 +179,8 @@ namespace {
 
 StepArgs step_args(const lbm_sim* s) {
   StepArgs a{};
-  a.fin = s->f(s->cur);
-  a.fout = s->f(1 - s->cur);
-  a.hin = s->h(s->cur);
-  a.hout = s->h(1 - s->cur);
-  a.pin = s->P(s->cur);
-  a.pout = s->P(1 - s->cur);
-  a.J = s->J();
+  a.sin = s->S(s->cur);
+  a.sout = s->S(1 - s->cur);
   a.phi = s->phi();
   a.status = s->status();
   a.g = s->L.g;
@@ -239,20 +230,13 @@ int pflbm::sim_params(const lbm_sim* s, lbm_params* out) {
   return LBM_OK;
 }
 
-void pflbm::sim_grid(const lbm_sim* s, int* pitch, long long* ps) {
-  *pitch = s->L.g.pitch;
-  *ps = s->L.g.ps;
-}
-
 Phys pflbm::sim_phys(const lbm_sim* s) { return s->c; }
 
 int pflbm::sim_view(const lbm_sim* s, SimView* v) {
   if (!s || !v) return fail(LBM_E_INVAL, "NULL argument");
-  v->f = s->f(s->cur);
-  v->P = s->P(s->cur);
-  v->h = s->h(s->cur);
-  v->J = s->J();
+  v->s = s->S(s->cur);
   v->phi = s->phi();
+  v->g = s->L.g;
   return LBM_OK;
 }
 
@@ -287,8 +271,8 @@ int lbm_init(lbm_sim** out, const lbm_params* p, void* d_ws, size_t ws_bytes, co
   s->step = 0;
   hipStream_t st = (hipStream_t)stream;
   Phys c = derive(p, 0.0);
-  // node-local initial populations go to buffer 1, the stored layout to buffer 0
-  hipError_t e = launch_init(d_phi0, d_ux0, d_uy0, s->f(1), s->h(1), s->f(0), s->h(0), s->J(), s->phi(), s->P(0), L.g, c, st);
+  // node-local initial populations go to state array 1, the stored layout to array 0
+  hipError_t e = launch_init(d_phi0, d_ux0, d_uy0, s->S(1), s->S(0), s->phi(), L.g, c, st);
   if (e == hipSuccess) e = launch_fill_int(s->status(), 0, 64, st);
   double rho0 = p->rho0;
   if (e == hipSuccess && std::isnan(p->rho0)) {
@@ -326,7 +310,7 @@ int lbm_step(lbm_sim* s, int32_t nsteps, int32_t form, void* stream) {
       if (int r = timer_stop(s, 0, slot, st)) return r;
       if (int r = timer_start(s, 1, st, &slot)) return r;
     }
-    HIPCHK(launch_phi(a.hout, s->phi(), s->L.g, s->c.wall_x, s->c.wall_y, st));
+    HIPCHK(launch_phi(a.sout, s->phi(), s->L.g, s->c.wall_x, s->c.wall_y, st));
     if (s->timing)
       if (int r = timer_stop(s, 1, slot, st)) return r;
     s->cur = 1 - s->cur;
@@ -359,44 +343,35 @@ int lbm_get_step(const lbm_sim* s, int64_t* step) {
   return LBM_OK;
 }
 
-// blob: [f 9 planes][h 9 planes][J 2 planes][P plane][phi FP64 plane][status]
+// blob: [state array, 21 interleaved planes][phi FP64 plane][status][zeros]
 int lbm_state_bytes(const lbm_sim* s, size_t* bytes) {
   if (!s || !bytes) return fail(LBM_E_INVAL, "NULL argument");
-  const size_t plane = (size_t)s->L.g.ps * sizeof(float);
-  *bytes = 21 * plane + (size_t)s->L.g.ps * sizeof(double) + kAlign;
+  *bytes = s->state_floats() * sizeof(float) + (size_t)s->L.g.ps * sizeof(double) + kAlign;
   return LBM_OK;
 }
 
 int lbm_save(lbm_sim* s, void* d_blob, void* stream) {
   if (!s || !d_blob) return fail(LBM_E_INVAL, "NULL argument");
   hipStream_t st = (hipStream_t)stream;
-  const size_t plane = (size_t)s->L.g.ps * sizeof(float);
+  const size_t sb = s->state_floats() * sizeof(float), pb = (size_t)s->L.g.ps * sizeof(double);
   char* b = (char*)d_blob;
-  HIPCHK(hipMemcpyAsync(b, s->f(s->cur), 9 * plane, hipMemcpyDeviceToDevice, st));
-  HIPCHK(hipMemcpyAsync(b + 9 * plane, s->h(s->cur), 9 * plane, hipMemcpyDeviceToDevice, st));
-  HIPCHK(hipMemcpyAsync(b + 18 * plane, s->J(), 2 * plane, hipMemcpyDeviceToDevice, st));
-  HIPCHK(hipMemcpyAsync(b + 20 * plane, s->P(s->cur), plane, hipMemcpyDeviceToDevice, st));
-  HIPCHK(hipMemcpyAsync(b + 21 * plane, s->phi(), (size_t)s->L.g.ps * sizeof(double), hipMemcpyDeviceToDevice, st));
-  HIPCHK(hipMemcpyAsync(b + 21 * plane + (size_t)s->L.g.ps * sizeof(double), s->status(), sizeof(int),
-                        hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(b, s->S(s->cur), sb, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(b + sb, s->phi(), pb, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(b + sb + pb, s->status(), sizeof(int), hipMemcpyDeviceToDevice, st));
   // the rest of the blob is zero, so equal states give equal blobs
   constexpr int kTailInts = (int)((kAlign - sizeof(int)) / sizeof(int));
-  HIPCHK(launch_fill_int((int*)(b + 21 * plane + (size_t)s->L.g.ps * sizeof(double) + sizeof(int)), 0, kTailInts, st));
+  HIPCHK(launch_fill_int((int*)(b + sb + pb + sizeof(int)), 0, kTailInts, st));
   return LBM_OK;
 }
 
 int lbm_restore(lbm_sim* s, const void* d_blob, void* stream) {
   if (!s || !d_blob) return fail(LBM_E_INVAL, "NULL argument");
   hipStream_t st = (hipStream_t)stream;
-  const size_t plane = (size_t)s->L.g.ps * sizeof(float);
+  const size_t sb = s->state_floats() * sizeof(float), pb = (size_t)s->L.g.ps * sizeof(double);
   const char* b = (const char*)d_blob;
-  HIPCHK(hipMemcpyAsync(s->f(s->cur), b, 9 * plane, hipMemcpyDeviceToDevice, st));
-  HIPCHK(hipMemcpyAsync(s->h(s->cur), b + 9 * plane, 9 * plane, hipMemcpyDeviceToDevice, st));
-  HIPCHK(hipMemcpyAsync(s->J(), b + 18 * plane, 2 * plane, hipMemcpyDeviceToDevice, st));
-  HIPCHK(hipMemcpyAsync(s->P(s->cur), b + 20 * plane, plane, hipMemcpyDeviceToDevice, st));
-  HIPCHK(hipMemcpyAsync(s->phi(), b + 21 * plane, (size_t)s->L.g.ps * sizeof(double), hipMemcpyDeviceToDevice, st));
-  HIPCHK(hipMemcpyAsync(s->status(), b + 21 * plane + (size_t)s->L.g.ps * sizeof(double), sizeof(int),
-                        hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(s->S(s->cur), b, sb, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(s->phi(), b + sb, pb, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(s->status(), b + sb + pb, sizeof(int), hipMemcpyDeviceToDevice, st));
   return LBM_OK;
 }
 

@@ -2,8 +2,8 @@
 //
 // `count` independent periodic lattices share one caller-provided workspace:
 //   [instance descriptors][tile list][status ints][rho0 sums][partial sums]
-//   then, per instance, the same planes as a single lattice (two f, h and P
-//   buffers, J, FP64 phi).
+//   then, per instance, the same arrays as a single lattice (two interleaved
+//   state arrays, FP64 phi).
 // A step is two persistent launches over one tile list covering every
 // instance (sorted by force form): the fused collide-stream kernel and the
 // order-parameter kernel.  Steps are replayed from a HIP graph captured once
@@ -42,7 +42,7 @@ size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct InstLayout {
   Grid g;
-  size_t f[2], h[2], P[2], J, phi;
+  size_t s[2], phi;
 };
 
 struct BatchLayout {
@@ -69,16 +69,14 @@ BatchLayout layout(const lbm_params* p, int count) {
     I.g.nx = p[k].nx;
     I.g.ny = p[k].ny;
     I.g.pitch = (p[k].nx + 63) / 64 * 64;   // as a single lattice, so results match bit for bit
+    I.g.ncx = I.g.pitch / 64;
     I.g.ps = (long long)I.g.pitch * p[k].ny;
-    I.g.psi = (int)I.g.ps;
-    I.g.fast = 36LL * I.g.ps < (1LL << 32) ? 1 : 0;
+    I.g.rowe = I.g.ncx * kSegE;
+    I.g.fast = 1;
     if (const char* e = std::getenv("PFLBM_GENERAL_PATH"))
       if (e[0] == '1') I.g.fast = 0;
-    const size_t plane = (size_t)I.g.ps * sizeof(float);
-    for (int b = 0; b < 2; ++b) { I.f[b] = o; o = up(o + 9 * plane); }
-    for (int b = 0; b < 2; ++b) { I.h[b] = o; o = up(o + 9 * plane); }
-    for (int b = 0; b < 2; ++b) { I.P[b] = o; o = up(o + plane); }
-    I.J = o; o = up(o + 2 * plane);
+    const size_t sbytes = (size_t)kNPL * (size_t)I.g.ps * sizeof(float);
+    for (int b = 0; b < 2; ++b) { I.s[b] = o; o = up(o + sbytes); }
     I.phi = o; o = up(o + (size_t)I.g.ps * sizeof(double));
   }
   L.total = o;
@@ -188,9 +186,8 @@ int lbm_batch_create(lbm_batch** out, const lbm_params* params, const int32_t* f
   for (int k = 0; k < count; ++k) {
     const InstLayout& I = b->L.inst[k];
     const Phys c0 = derive_phys(&params[k], 0.0);
-    hipError_t e = launch_init(d_phi0[k], nullptr, nullptr, (float*)(ws + I.f[1]), (float*)(ws + I.h[1]),
-                               (float*)(ws + I.f[0]), (float*)(ws + I.h[0]), (float*)(ws + I.J),
-                               (double*)(ws + I.phi), (float*)(ws + I.P[0]), I.g, c0, st);
+    hipError_t e = launch_init(d_phi0[k], nullptr, nullptr, (float*)(ws + I.s[1]), (float*)(ws + I.s[0]),
+                               (double*)(ws + I.phi), I.g, c0, st);
     if (e == hipSuccess)
       e = launch_phi_sum((double*)(ws + I.phi), I.g, (double*)(ws + b->L.partial) + (size_t)k * kPartials, kPartials,
                          (double*)(ws + b->L.sums) + k, st);
@@ -214,13 +211,8 @@ int lbm_batch_create(lbm_batch** out, const lbm_params* params, const int32_t* f
     const Phys c = derive_phys(&p, rho0);
     for (int par = 0; par < 2; ++par) {
       StepArgs& a = b->host[k].a[par];
-      a.fin = (const float*)(ws + I.f[par]);
-      a.fout = (float*)(ws + I.f[1 - par]);
-      a.hin = (const float*)(ws + I.h[par]);
-      a.hout = (float*)(ws + I.h[1 - par]);
-      a.pin = (const float*)(ws + I.P[par]);
-      a.pout = (float*)(ws + I.P[1 - par]);
-      a.J = (float*)(ws + I.J);
+      a.sin = (const float*)(ws + I.s[par]);
+      a.sout = (float*)(ws + I.s[1 - par]);
       a.phi = (const double*)(ws + I.phi);
       a.status = b->d_status() + k;
       a.g = I.g;

@@ -2,15 +2,17 @@
 //
 // D2Q9 lattice of arXiv:2012.14729, Sec. III (Eq. 34 and the weights below
 // it), stored as constexpr functions so fully unrolled loops fold them into
-// immediates.  Device state layout (structure of arrays, x fastest):
-//   f[2][9] planes  FP32  post-collision flow populations minus w_i P of the
-//                         storing node (ping-pong)
-//   P[2]    planes  FP32  pressure P_sf of the storing node (ping-pong)
-//   h[2][9] planes  FP32  post-collision order-parameter populations; slot 0
-//                         holds d0 = h_0^+ - phi (a small deviation) instead of h_0^+
-//   J[2]    planes  FP32  (phi u) of the previous step, updated in place
-//   phi     plane   FP64  order parameter, updated in place
-// A plane is `pitch * ny` elements; element (x, y) is at y * pitch + x.
+// immediates.  Device state of one lattice (x fastest, pitch = nx rounded up
+// to 64):
+//   S[2]  FP32 ping-pong state arrays of 21 planes, interleaved in row
+//         segments of 64 nodes: element (plane p, x, y) lies at
+//         ((y * ncx + x / 64) * 21 + p) * 64 + x % 64  (ncx = pitch / 64), so
+//         the 21 values of a 64-node row segment are one 5376-byte run.
+//         planes 0-8   f_i - w_i P of the storing node (post-collision)
+//         planes 9-17  h_i (post-collision); plane 9 holds d0 = h_0^+ - phi
+//         plane 18     P_sf of the storing node
+//         planes 19-20 (phi u) of the step that stored them
+//   phi   FP64 plane (pitch * ny), updated in place
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -23,6 +25,10 @@ __host__ __device__ constexpr int cy(int i) { return (i == 2 || i == 5 || i == 6
 __host__ __device__ constexpr float wt(int i) { return i == 0 ? 4.0f / 9.0f : (i < 5 ? 1.0f / 9.0f : 1.0f / 36.0f); }
 __host__ __device__ constexpr double wtd(int i) { return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0); }
 __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : (i < 5 ? ((i + 1) % 4) + 1 : ((i - 3) % 4) + 5); }
+
+constexpr int kNPL = 21;  // planes of a state array
+constexpr int kPF = 0, kPH = 9, kPP = 18, kPJ = 19;   // first plane of f, h, P, J
+constexpr int kSegE = kNPL * 64;   // elements of one interleaved row segment
 
 constexpr int kTX = 64;   // tile width  (one wavefront row)
 constexpr int kTY = 8;    // tile height
@@ -48,21 +54,23 @@ struct Phys {
 
 struct Grid {
   int nx, ny, pitch;
-  long long ps;           // plane stride in elements
-  int psi;                // the same as int (9 * ps < 2^31 is validated)
-  int fast;               // 36 * ps < 2^32: byte offsets into a 9-plane FP32 array fit 32 bits
+  int ncx;                // 64-node row segments per row (pitch / 64)
+  long long ps;           // nodes of a padded plane (pitch * ny)
+  int rowe;               // elements of one row of a state array (ncx * 21 * 64)
+  int fast;               // interior tiles may take the fast addressing path
 };
 
+// Element index of plane 0 of node (x, y) in a state array (21 ps < 2^32 is
+// validated); plane p of the node is 64 p elements further.
+__host__ __device__ __forceinline__ unsigned nbase(const Grid& g, int x, int y) {
+  return (unsigned)(y * g.ncx + (x >> 6)) * (unsigned)kSegE + (unsigned)(x & 63);
+}
+
 struct StepArgs {
-  const float* fin;
-  float* fout;
-  const float* pin;
-  float* pout;
-  const float* hin;
-  float* hout;
-  float* J;
-  const double* phi;
-  int* status;
+  const float* sin;       // state array holding the current step
+  float* sout;            // state array receiving the next step
+  const double* phi;      // order parameter (read by the fused kernel, updated by k_phi)
+  int* status;            // divergence flag
   Grid g;
   Phys c;
 };
@@ -102,24 +110,20 @@ struct lbm_sim;
 namespace pflbm {
 // Read access to a single lattice's current state (lbm_api.hip).
 struct SimView {
-  const float* f;     // 9 planes: f_i - w_i P of the storing node
-  const float* P;     // pressure of the storing node
-  const float* h;     // 9 planes (slot 0: d0)
-  const float* J;     // 2 planes
+  const float* s;     // state array of the current step (layout above)
   const double* phi;  // order parameter (current)
+  Grid g;
 };
 int sim_params(const lbm_sim* s, lbm_params* out);
-void sim_grid(const lbm_sim* s, int* pitch, long long* ps);
 Phys sim_phys(const lbm_sim* s);
 int sim_view(const lbm_sim* s, SimView* v);
 
 // kernel launchers (lbm_kernels.hip); each returns the launch error code
 hipError_t launch_fused(int form, const StepArgs& a, hipStream_t s);
 hipError_t launch_moments(int form, const StepArgs& a, const MomentArgs& m, hipStream_t s);
-hipError_t launch_phi(const float* h, double* phi, const Grid& g, int wall_x, int wall_y, hipStream_t s);
-hipError_t launch_init(const float* phi0, const float* ux0, const float* uy0, float* f_tmp, float* h_tmp,
-                       float* f_out, float* h_out, float* J, double* phi, float* P, const Grid& g, const Phys& c,
-                       hipStream_t s);
+hipError_t launch_phi(const float* snew, double* phi, const Grid& g, int wall_x, int wall_y, hipStream_t s);
+hipError_t launch_init(const float* phi0, const float* ux0, const float* uy0, float* s_tmp, float* s0, double* phi,
+                       const Grid& g, const Phys& c, hipStream_t s);
 hipError_t launch_phi_sum(const double* phi, const Grid& g, double* partial, int npartial, double* out,
                           hipStream_t s);
 hipError_t launch_fill_int(int* p, int value, int n, hipStream_t s);

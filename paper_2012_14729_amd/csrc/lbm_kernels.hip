@@ -4,14 +4,15 @@
 // One time step is two launches:
 //   k_fused<FORM>  pull-stream f and h (with bounce-back), compute phi
 //                  stencils, mu_phi, the interfacial force, u, P, div(phi u),
-//                  d_t(phi u), collide both populations and store them
-//                  (structure of arrays, coalesced rows).
+//                  d_t(phi u), collide both populations and store them.
 //   k_phi          phi^{n+1} = phi^n + d0 + sum_{i>=1} h_i pulled, in FP64.
 //
 // The fused kernel works on 64x8 tiles.  The order parameter is staged in LDS
 // with a 3-node halo (FP64); second-level stencil fields live on the 2-node
 // ring, the velocity on the 1-node ring.  Only nearest-neighbour pulls touch
-// HBM; everything with a wider footprint comes from LDS.
+// HBM; everything with a wider footprint comes from LDS.  The state arrays
+// interleave their 21 planes in 64-node row segments (lbm_internal.hpp), so a
+// wavefront's loads and stores of one row segment form one contiguous run.
 #include "lbm_internal.hpp"
 
 namespace pflbm {
@@ -51,13 +52,13 @@ __device__ __forceinline__ int halo_coord(int c, int n) {
   }
 }
 
-// Source of the pulled population i for node (x, y) inside the domain: the
-// value that left x - c_i in direction i; if x - c_i lies beyond a wall the
-// slot opp(i) of x itself holds the bounced population (the wall term is
-// applied when it is stored).  Returns the node offset; `slot` the plane.
-// Offsets are 32-bit: a simulation holds fewer than 2^31 elements per buffer.
+// Source of the pulled population I for node (x, y) inside the domain: the
+// value that left x - c_I in direction I; if x - c_I lies beyond a wall the
+// slot opp(I) of x itself holds the bounced population (the wall term is
+// applied when it is stored).  Returns the element index of plane 0 of the
+// source node in a state array; `slot` is the direction to read there.
 template <int I>
-__device__ __forceinline__ int src_off(int x, int y, const Grid& g, int wx, int wy, int& slot) {
+__device__ __forceinline__ unsigned src_base(int x, int y, const Grid& g, int wx, int wy, int& slot) {
   int sx = x - cx(I), sy = y - cy(I);
   bool bounce = false;
   if (cx(I) != 0) {
@@ -69,46 +70,48 @@ __device__ __forceinline__ int src_off(int x, int y, const Grid& g, int wx, int 
     sy = sy < 0 ? sy + g.ny : (sy >= g.ny ? sy - g.ny : sy);
   }
   slot = bounce ? opp(I) : I;
-  return bounce ? y * g.pitch + x : sy * g.pitch + sx;
-}
-
-template <int I>
-__device__ __forceinline__ float pull(const float* __restrict__ base, int x, int y, const Grid& g, int wx, int wy) {
-  int sl;
-  const int o = src_off<I>(x, y, g, wx, wy, sl);
-  return base[(unsigned)(sl * g.psi + o)];
+  return bounce ? nbase(g, x, y) : nbase(g, sx, sy);
 }
 
 // Interior tiles (every pull and every halo position inside the domain)
-// address memory as one uniform base pointer per array plus a 32-bit
-// per-thread byte offset (the SGPR-base global load/store forms).  The plane
-// index and the source shift of a pulled population are one uniform term
-// added to the node's byte offset: the f and h pulls of a direction share
-// that offset, so an access costs at most one 32-bit vector add.
+// address a state array from a uniform tile origin with a 32-bit per-thread
+// byte offset; the row shift of a pull and the plane are uniform constants,
+// so a load or store is one SGPR-base + VGPR-offset + immediate access with
+// no vector address arithmetic.  Values used once (a node's own pulled
+// populations and (phi u), every store) go through the non-temporal path;
+// the source pressures and the ring's pulls, which neighbours read again,
+// do not.
 template <class T>
-__device__ __forceinline__ T ldb(const T* base, unsigned off) {
-  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+__device__ __forceinline__ const T* at(const T* base, unsigned boff) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + boff);
 }
 template <class T>
-__device__ __forceinline__ void stb(T* base, unsigned off, T v) {
-  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off) = v;
+__device__ __forceinline__ T* at(T* base, unsigned boff) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff);
 }
-// Byte offset, within a 9-plane FP32 array, of population I pulled by the
-// node at byte offset ob: plane I at the node x - c_I.  Below 2^32 when
-// Grid::fast is set (36 ps < 2^32); the arithmetic is modulo 2^32.
-template <int I>
-__device__ __forceinline__ unsigned pull_off(const Grid& g, unsigned ob) {
-  return ob + 4u * (unsigned)I * (unsigned)g.psi - 4u * (unsigned)(cx(I) + cy(I) * g.pitch);
+__device__ __forceinline__ float ld_nt(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void st_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
+
+// Byte offsets, from an interior tile's input origin (plane 0 of node
+// (x0 - 64, y0 - 2)), of plane 0 of the nodes (xr - 1 + k, yr), k = 0, 1, 2,
+// where (xr, yr) is relative to the tile corner (x0, y0).  A pull of
+// direction I by node (xr, yr) reads v3[1 - c_Ix] from the origin moved by
+// -c_Iy rows.
+__device__ __forceinline__ void node_offsets(const Grid& g, int xr, int yr, unsigned* v3) {
+  const int row = (yr + 2) * g.rowe;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int xs = xr + k - 1;
+    v3[k] = 4u * (unsigned)(row + ((xs >> 6) + 1) * kSegE + (xs & 63));
+  }
 }
-// Byte offset of the node x - c_I in a single plane (x - c_I is inside the
-// domain for an interior tile, so the difference is non-negative).
-template <int I>
-__device__ __forceinline__ unsigned src_off_b(const Grid& g, unsigned ob) {
-  return ob - 4u * (unsigned)(cx(I) + cy(I) * g.pitch);
-}
-template <int I>
-__device__ __forceinline__ float pull_fast(const float* planes, const Grid& g, unsigned ob) {
-  return ldb(planes, pull_off<I>(g, ob));
+
+// Population plane P pulled in direction I by the node with offsets v3.
+template <int I, int P, bool NT>
+__device__ __forceinline__ float pull_tile(const float* tin, int rowe, const unsigned* v3) {
+  const float* q = at(tin - (long long)cy(I) * rowe + P * 64, v3[1 - cx(I)]);
+  if constexpr (NT) return ld_nt(q);
+  else return *q;
 }
 
 // 1/x in FP64 from an FP32 seed and two Newton steps (exact to ~1 ulp for
@@ -285,9 +288,9 @@ __device__ __forceinline__ void load_fp(const StepArgs& a, int x, int y, float* 
 #define PULL_FP(I)                                               \
   {                                                              \
     int sl_;                                                     \
-    const int o_ = src_off<I>(x, y, a.g, wx, wy, sl_);           \
-    ft[I] = a.fin[(unsigned)(sl_ * a.g.psi + o_)];               \
-    ps[I] = a.pin[(unsigned)o_];                                 \
+    const unsigned b_ = src_base<I>(x, y, a.g, wx, wy, sl_);     \
+    ft[I] = a.sin[b_ + (unsigned)((kPF + sl_) * 64)];            \
+    ps[I] = a.sin[b_ + (unsigned)(kPP * 64)];                    \
   }
   PULL_FP(0) PULL_FP(1) PULL_FP(2) PULL_FP(3) PULL_FP(4) PULL_FP(5) PULL_FP(6) PULL_FP(7) PULL_FP(8)
 #undef PULL_FP
@@ -390,19 +393,19 @@ __device__ __forceinline__ float dotcf(int i, float vx, float vy) {
   return tx + ty;
 }
 
-// Pulled flow populations and source pressures of a node of an interior tile.
-__device__ __forceinline__ void load_fp_fast(const StepArgs& a, unsigned ob, float* ft, float* ps) {
-#define PULL_FP_FAST(I)                         \
-  ft[I] = pull_fast<I>(a.fin, a.g, ob);         \
-  ps[I] = ldb(a.pin, src_off_b<I>(a.g, ob));
-  PULL_FP_FAST(0) PULL_FP_FAST(1) PULL_FP_FAST(2) PULL_FP_FAST(3) PULL_FP_FAST(4)
-  PULL_FP_FAST(5) PULL_FP_FAST(6) PULL_FP_FAST(7) PULL_FP_FAST(8)
-#undef PULL_FP_FAST
+// Pulled flow populations and source pressures of a node of an interior
+// tile (offsets v3, see node_offsets).
+template <bool NT>
+__device__ __forceinline__ void load_fp_tile(const float* tin, int rowe, const unsigned* v3, float* ft, float* ps) {
+#define PULL_FT(I)                                   \
+  ft[I] = pull_tile<I, kPF + I, NT>(tin, rowe, v3);  \
+  ps[I] = pull_tile<I, kPP, false>(tin, rowe, v3);
+  PULL_FT(0) PULL_FT(1) PULL_FT(2) PULL_FT(3) PULL_FT(4) PULL_FT(5) PULL_FT(6) PULL_FT(7) PULL_FT(8)
+#undef PULL_FT
 }
 
 // A tile is interior when every position it reads (the phi halo reaches 3
-// nodes past the tile) lies inside the domain: no wrap, mirror or bounce;
-// its 32-bit byte offsets need Grid::fast.
+// nodes past the tile) lies inside the domain: no wrap, mirror or bounce.
 __device__ __forceinline__ bool interior_tile(int x0, int y0, const Grid& g) {
   return g.fast && x0 >= 3 && y0 >= 3 && x0 + kTX + 3 <= g.nx && y0 + kTY + 3 <= g.ny;
 }
@@ -421,10 +424,10 @@ __device__ __forceinline__ bool wall_hit(int x, int y, const Grid& g, const Phys
 
 // Collision results of one opposite pair (I, J = opp(I)) of both population
 // sets, stored with the wall term applied (general tiles) or directly
-// (interior tiles).
+// (interior tiles: output origin tout, byte offset ob).
 template <int I, bool FAST, bool WX, bool WY>
-__device__ __forceinline__ void store_pair(const StepArgs& a, int x, int y, unsigned o, unsigned ob, double fpi,
-                                           double fpj, double hpi, double hpj, double rho, double phid,
+__device__ __forceinline__ void store_pair(const StepArgs& a, int x, int y, unsigned on, float* tout, unsigned ob,
+                                           double fpi, double fpj, double hpi, double hpj, double rho, double phid,
                                            double& d0sum) {
   constexpr int J = opp(I);
   if constexpr (!FAST) {
@@ -435,16 +438,15 @@ __device__ __forceinline__ void store_pair(const StepArgs& a, int x, int y, unsi
   const float hsi = (float)hpi, hsj = (float)hpj;
   d0sum += (double)hsi + (double)hsj;
   if constexpr (FAST) {
-    const unsigned oi = ob + 4u * (unsigned)I * (unsigned)a.g.psi, oj = ob + 4u * (unsigned)J * (unsigned)a.g.psi;
-    stb(a.fout, oi, (float)fpi);
-    stb(a.fout, oj, (float)fpj);
-    stb(a.hout, oi, hsi);
-    stb(a.hout, oj, hsj);
+    st_nt(at(tout + (kPF + I) * 64, ob), (float)fpi);
+    st_nt(at(tout + (kPF + J) * 64, ob), (float)fpj);
+    st_nt(at(tout + (kPH + I) * 64, ob), hsi);
+    st_nt(at(tout + (kPH + J) * 64, ob), hsj);
   } else {
-    a.fout[(unsigned)(I * a.g.psi) + o] = (float)fpi;
-    a.fout[(unsigned)(J * a.g.psi) + o] = (float)fpj;
-    a.hout[(unsigned)(I * a.g.psi) + o] = hsi;
-    a.hout[(unsigned)(J * a.g.psi) + o] = hsj;
+    a.sout[on + (unsigned)((kPF + I) * 64)] = (float)fpi;
+    a.sout[on + (unsigned)((kPF + J) * 64)] = (float)fpj;
+    a.sout[on + (unsigned)((kPH + I) * 64)] = hsi;
+    a.sout[on + (unsigned)((kPH + J) * 64)] = hsj;
   }
 }
 
@@ -462,27 +464,34 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
   const int uy_ = ty + 1, ux_ = lx + 1;             // velocity-ring coordinates of this node
   int x, y;
   bool valid, act;
+  const float* tin = nullptr;   // interior tiles: input origin (node (x0 - 64, y0 - 2))
+  float* tout = nullptr;        // interior tiles: output origin (node (x0, y0))
   if constexpr (FAST) {
     x = x0 + lx;
     y = y0 + ty;
     valid = act = true;
+    tin = a.sin + nbase(g, x0 - 64, y0 - 2);
+    tout = a.sout + nbase(g, x0, y0);
   } else {
     valid = ring_global<WX, WY>(uy_, ux_, x0, y0, a, x, y);
     act = (x0 + lx < g.nx) && (y0 + ty < g.ny);
   }
-  const unsigned o = (unsigned)(y * g.pitch + x);   // node offset (valid nodes)
-  const unsigned ob = o * 4u;                       // its byte offset in an FP32 plane
+  const unsigned on = nbase(g, x, y);   // general path: plane 0 of this node (valid nodes)
 
   // This node's flow populations are pulled after the ring velocities (the
   // ring threads would otherwise hold both sets of registers at once).
   float ft[9], ps[9], h[9];
   float j0 = 0.f, j1 = 0.f;
   // Stage A: phi tile with a 3-node halo (periodic wrap / even reflection at walls, Sec. IV)
-  for (int k = tid; k < PH * PW; k += kFusedThreads) {
-    const int py = k / PW, px = k - py * PW;
-    if constexpr (FAST) {
-      s.phi[py][px] = ldb(a.phi, (unsigned)((y0 + py - 3) * g.pitch + (x0 + px - 3)) * 8u);   // < 8 ps < 2^32
-    } else {
+  if constexpr (FAST) {
+    const double* tphi = a.phi + ((long long)(y0 - 3) * g.pitch + (x0 - 3));
+    for (int k = tid; k < PH * PW; k += kFusedThreads) {
+      const int py = k / PW, px = k - py * PW;
+      s.phi[py][px] = *at(tphi, (unsigned)(py * g.pitch + px) * 8u);
+    }
+  } else {
+    for (int k = tid; k < PH * PW; k += kFusedThreads) {
+      const int py = k / PW, px = k - py * PW;
       const int gx = halo_coord<WX>(x0 + px - 3, g.nx);
       const int gy = halo_coord<WY>(y0 + py - 3, g.ny);
       s.phi[py][px] = a.phi[(unsigned)(gy * g.pitch + gx)];
@@ -501,7 +510,9 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
       float rft[9], rps[9];
       bool ok = true;
       if constexpr (FAST) {
-        load_fp_fast(a, (unsigned)((y0 + ruy - 1) * g.pitch + (x0 + rux - 1)) * 4u, rft, rps);
+        unsigned rv[3];
+        node_offsets(g, rux - 1, ruy - 1, rv);
+        load_fp_tile<false>(tin, g.rowe, rv, rft, rps);
       } else {
         int rx, ry;
         ok = ring_global<WX, WY>(ruy, rux, x0, y0, a, rx, ry);
@@ -517,8 +528,10 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
     }
   }
   NodeState n;
+  unsigned v3[3] = {0u, 0u, 0u};
+  if constexpr (FAST) node_offsets(g, lx, ty, v3);
   if (valid) {
-    if constexpr (FAST) load_fp_fast(a, ob, ft, ps);
+    if constexpr (FAST) load_fp_tile<true>(tin, g.rowe, v3, ft, ps);
     else load_fp<WX, WY>(a, x, y, ft, ps);
     velocity_from<FORM, true>(s, a, uy_, ux_, ft, ps, n);
     if constexpr (!MOMENTS) {
@@ -540,31 +553,29 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
   } else {
     __syncthreads();
     if (!act) return;
-    {
-      if constexpr (FAST) {
-        h[1] = pull_fast<1>(a.hin, g, ob);
-        h[2] = pull_fast<2>(a.hin, g, ob);
-        h[3] = pull_fast<3>(a.hin, g, ob);
-        h[4] = pull_fast<4>(a.hin, g, ob);
-        h[5] = pull_fast<5>(a.hin, g, ob);
-        h[6] = pull_fast<6>(a.hin, g, ob);
-        h[7] = pull_fast<7>(a.hin, g, ob);
-        h[8] = pull_fast<8>(a.hin, g, ob);
-        j0 = ldb((const float*)a.J, ob);
-        j1 = ldb((const float*)a.J, ob + 4u * (unsigned)g.psi);
-      } else {
-        constexpr int wx = WX, wy = WY;
-        h[1] = pull<1>(a.hin, x, y, g, wx, wy);
-        h[2] = pull<2>(a.hin, x, y, g, wx, wy);
-        h[3] = pull<3>(a.hin, x, y, g, wx, wy);
-        h[4] = pull<4>(a.hin, x, y, g, wx, wy);
-        h[5] = pull<5>(a.hin, x, y, g, wx, wy);
-        h[6] = pull<6>(a.hin, x, y, g, wx, wy);
-        h[7] = pull<7>(a.hin, x, y, g, wx, wy);
-        h[8] = pull<8>(a.hin, x, y, g, wx, wy);
-        j0 = a.J[o];
-        j1 = a.J[(unsigned)g.psi + o];
-      }
+    if constexpr (FAST) {
+      h[1] = pull_tile<1, kPH + 1, true>(tin, g.rowe, v3);
+      h[2] = pull_tile<2, kPH + 2, true>(tin, g.rowe, v3);
+      h[3] = pull_tile<3, kPH + 3, true>(tin, g.rowe, v3);
+      h[4] = pull_tile<4, kPH + 4, true>(tin, g.rowe, v3);
+      h[5] = pull_tile<5, kPH + 5, true>(tin, g.rowe, v3);
+      h[6] = pull_tile<6, kPH + 6, true>(tin, g.rowe, v3);
+      h[7] = pull_tile<7, kPH + 7, true>(tin, g.rowe, v3);
+      h[8] = pull_tile<8, kPH + 8, true>(tin, g.rowe, v3);
+      j0 = pull_tile<0, kPJ, true>(tin, g.rowe, v3);
+      j1 = pull_tile<0, kPJ + 1, true>(tin, g.rowe, v3);
+    } else {
+      constexpr int wx = WX, wy = WY;
+#define PULL_HG(I)                                                 \
+  {                                                                \
+    int sl_;                                                       \
+    const unsigned b_ = src_base<I>(x, y, g, wx, wy, sl_);         \
+    h[I] = a.sin[b_ + (unsigned)((kPH + sl_) * 64)];               \
+  }
+      PULL_HG(1) PULL_HG(2) PULL_HG(3) PULL_HG(4) PULL_HG(5) PULL_HG(6) PULL_HG(7) PULL_HG(8)
+#undef PULL_HG
+      j0 = a.sin[on + (unsigned)(kPJ * 64)];
+      j1 = a.sin[on + (unsigned)((kPJ + 1) * 64)];
     }
 
     const int py = uy_ + 2, px = ux_ + 2;
@@ -599,14 +610,15 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
     const double dq = 3.0 * (double)dqf;
     const double qx = phid * n.ux, qy = phid * n.uy;
     const double dtx = qx - (double)j0, dty = qy - (double)j1;   // explicit-Euler d_t(phi u) (A4)
+    const unsigned ob = 4u * (unsigned)(ty * g.rowe + lx);        // interior: this node from tout
     if constexpr (FAST) {
-      stb(a.J, ob, (float)qx);
-      stb(a.J, ob + 4u * (unsigned)g.psi, (float)qy);
-      stb(a.pout, ob, n.Pn);
+      st_nt(at(tout + kPJ * 64, ob), (float)qx);
+      st_nt(at(tout + (kPJ + 1) * 64, ob), (float)qy);
+      st_nt(at(tout + kPP * 64, ob), n.Pn);
     } else {
-      a.J[o] = (float)qx;
-      a.J[(unsigned)g.psi + o] = (float)qy;
-      a.pout[o] = n.Pn;
+      a.sout[on + (unsigned)(kPJ * 64)] = (float)qx;
+      a.sout[on + (unsigned)((kPJ + 1) * 64)] = (float)qy;
+      a.sout[on + (unsigned)(kPP * 64)] = n.Pn;
     }
 
     if (!(isfinite(n.ux) && isfinite(n.uy) && isfinite(phid))) atomicOr(a.status, 1);
@@ -646,8 +658,8 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
     double d0sum = 0.0;   // sum of the stored h_i^+ (i >= 1)
     {
       const double fp0 = keep_f * (double)n.f[0] + wtd(0) * fma(m15usq, K1, K0);
-      if constexpr (FAST) stb(a.fout, ob, (float)fp0);
-      else a.fout[o] = (float)fp0;
+      if constexpr (FAST) st_nt(at(tout + kPF * 64, ob), (float)fp0);
+      else a.sout[on + (unsigned)(kPF * 64)] = (float)fp0;
     }
 #define COLLIDE_PAIR(I)                                                                        \
   {                                                                                            \
@@ -662,15 +674,15 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
     const double wG = wtd(I) * G0, t = (3.0 * wtd(I)) * dotc(I, Vx, Vy);                      \
     const double hpi = fma(keep_h, (double)h[I], wG + t);                                      \
     const double hpj = fma(keep_h, (double)h[J_], wG - t);                                     \
-    store_pair<I, FAST, WX, WY>(a, x, y, o, ob, fpi, fpj, hpi, hpj, n.rho, phid, d0sum);       \
+    store_pair<I, FAST, WX, WY>(a, x, y, on, tout, ob, fpi, fpj, hpi, hpj, n.rho, phid, d0sum); \
   }
     COLLIDE_PAIR(1) COLLIDE_PAIR(2) COLLIDE_PAIR(5) COLLIDE_PAIR(6)
 #undef COLLIDE_PAIR
     // slot 0 holds d0 = h_0^+ - phi.  The collision conserves sum_i h_i = phi
     // (Eqs. 32 and 36), so d0 = -sum_{i>=1} h_i^+ exactly; forming it from
     // the stored values makes the update of phi conservative.
-    if constexpr (FAST) stb(a.hout, ob, (float)(-d0sum));
-    else a.hout[o] = (float)(-d0sum);
+    if constexpr (FAST) st_nt(at(tout + kPH * 64, ob), (float)(-d0sum));
+    else a.sout[on + (unsigned)(kPH * 64)] = (float)(-d0sum);
   }
 }
 
@@ -693,32 +705,55 @@ __global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(4
   fused_tile<FORM, MOMENTS, BC>(s, a, m, tile_x, tile_y);
 }
 
-// phi^{n+1}(x) = phi^n(x) + d0(x) + sum_{i>=1} h_i^+(x - c_i)   (Eq. 37, phi = sum h_i)
-template <int BC>
-__device__ __forceinline__ void phi_tile(const float* __restrict__ h, double* __restrict__ phi, const Grid& g,
-                                         int tile_x, int tile_y) {
+// phi^{n+1}(x) = phi^n(x) + d0(x) + sum_{i>=1} h_i^+(x - c_i)   (Eq. 37,
+// phi = sum h_i), from the state array just written (snew).  Both paths sum
+// in the same order.
+template <int BC, bool FAST>
+__device__ __forceinline__ void phi_tile_impl(const float* __restrict__ snew, double* __restrict__ phi, const Grid& g,
+                                              int tile_x, int tile_y) {
   constexpr int wx = (BC & 1) != 0, wy = (BC & 2) != 0;
-  const int x = tile_x * kTX + (threadIdx.x & (kTX - 1));
-  const int y = tile_y * kTY + threadIdx.x / kTX;
+  const int lx = threadIdx.x & (kTX - 1), ty = threadIdx.x / kTX;
+  const int x = tile_x * kTX + lx, y = tile_y * kTY + ty;
   if (x >= g.nx || y >= g.ny) return;
-  const int o = y * g.pitch + x;
-  double s = (double)h[(unsigned)o];
-  s += (double)pull<1>(h, x, y, g, wx, wy);
-  s += (double)pull<2>(h, x, y, g, wx, wy);
-  s += (double)pull<3>(h, x, y, g, wx, wy);
-  s += (double)pull<4>(h, x, y, g, wx, wy);
-  s += (double)pull<5>(h, x, y, g, wx, wy);
-  s += (double)pull<6>(h, x, y, g, wx, wy);
-  s += (double)pull<7>(h, x, y, g, wx, wy);
-  s += (double)pull<8>(h, x, y, g, wx, wy);
-  phi[(unsigned)o] += s;
+  double sum;
+  if constexpr (FAST) {
+    const float* tin = snew + nbase(g, tile_x * kTX - 64, tile_y * kTY - 2);
+    unsigned v3[3];
+    node_offsets(g, lx, ty, v3);
+    sum = (double)pull_tile<0, kPH, true>(tin, g.rowe, v3);
+    sum += (double)pull_tile<1, kPH + 1, true>(tin, g.rowe, v3);
+    sum += (double)pull_tile<2, kPH + 2, true>(tin, g.rowe, v3);
+    sum += (double)pull_tile<3, kPH + 3, true>(tin, g.rowe, v3);
+    sum += (double)pull_tile<4, kPH + 4, true>(tin, g.rowe, v3);
+    sum += (double)pull_tile<5, kPH + 5, true>(tin, g.rowe, v3);
+    sum += (double)pull_tile<6, kPH + 6, true>(tin, g.rowe, v3);
+    sum += (double)pull_tile<7, kPH + 7, true>(tin, g.rowe, v3);
+    sum += (double)pull_tile<8, kPH + 8, true>(tin, g.rowe, v3);
+  } else {
+    sum = (double)snew[nbase(g, x, y) + (unsigned)(kPH * 64)];
+#define PULL_PH(I)                                               \
+  {                                                              \
+    int sl_;                                                     \
+    const unsigned b_ = src_base<I>(x, y, g, wx, wy, sl_);       \
+    sum += (double)snew[b_ + (unsigned)((kPH + sl_) * 64)];      \
+  }
+    PULL_PH(1) PULL_PH(2) PULL_PH(3) PULL_PH(4) PULL_PH(5) PULL_PH(6) PULL_PH(7) PULL_PH(8)
+#undef PULL_PH
+  }
+  phi[(long long)y * g.pitch + x] += sum;
 }
 
 template <int BC>
-__global__ __launch_bounds__(kFusedThreads) void k_phi(const float* __restrict__ h, double* __restrict__ phi, Grid g) {
+__device__ __forceinline__ void phi_tile(const float* snew, double* phi, const Grid& g, int tile_x, int tile_y) {
+  if (interior_tile(tile_x * kTX, tile_y * kTY, g)) phi_tile_impl<BC, true>(snew, phi, g, tile_x, tile_y);
+  else phi_tile_impl<BC, false>(snew, phi, g, tile_x, tile_y);
+}
+
+template <int BC>
+__global__ __launch_bounds__(kFusedThreads) void k_phi(const float* __restrict__ snew, double* __restrict__ phi, Grid g) {
   int tx, ty;
   if (!xcd_tile((g.nx + kTX - 1) / kTX, (g.ny + kTY - 1) / kTY, tx, ty)) return;
-  phi_tile<BC>(h, phi, g, tx, ty);
+  phi_tile<BC>(snew, phi, g, tx, ty);
 }
 
 // Batched step: persistent workgroups walk a tile list covering every
@@ -764,20 +799,20 @@ __global__ __launch_bounds__(kFusedThreads) void k_batch_phi(const BatchInst* __
   for (int t = first; t < end; t += stride) {
     const TileRef tr = tiles[t];
     const StepArgs& a = inst[tr.inst].a[parity];
-    phi_tile<0>(a.hout, const_cast<double*>(a.phi), a.g, tr.tx, tr.ty);
+    phi_tile<0>(a.sout, const_cast<double*>(a.phi), a.g, tr.tx, tr.ty);
   }
 }
 
 // Initial state, pass 1: node-local f^eq(P = 0, rho(phi0), u0) and
-// h^eq(phi0, mu(phi0), u0) (Eqs. 31-32; reading A11), phi (FP64), J = phi0 u0.
+// h^eq(phi0, mu(phi0), u0) (Eqs. 31-32; reading A11) into the f and h planes
+// of s_tmp; phi (FP64); P = 0 and (phi u) = phi0 u0 into s0.
 __global__ __launch_bounds__(256) void k_init_local(const float* __restrict__ phi0, const float* __restrict__ ux0,
-                                                    const float* __restrict__ uy0, float* __restrict__ ft,
-                                                    float* __restrict__ ht, float* __restrict__ J,
-                                                    double* __restrict__ phi, float* __restrict__ P, Grid g, Phys c) {
+                                                    const float* __restrict__ uy0, float* __restrict__ s_tmp,
+                                                    float* __restrict__ s0, double* __restrict__ phi, Grid g, Phys c) {
   const int x = blockIdx.x * 64 + (threadIdx.x & 63);
   const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (x >= g.nx || y >= g.ny) return;
-  const long long o = (long long)y * g.pitch + x;
+  const unsigned on = nbase(g, x, y);
   const double p0 = (double)phi0[(long long)y * g.nx + x];
   double sl = 0.0;
 #pragma unroll
@@ -796,35 +831,35 @@ __global__ __launch_bounds__(256) void k_init_local(const float* __restrict__ ph
   for (int i = 0; i < 9; ++i) {
     const float cu = (float)cx(i) * ux + (float)cy(i) * uy;
     const float si = 3.0f * cu + 4.5f * cu * cu - 1.5f * usq;
-    ft[(long long)i * g.ps + o] = wt(i) * CS2 * rho * si;
-    ht[(long long)i * g.ps + o] = (i == 0) ? 0.0f : wt(i) * etamu + wt(i) * (float)p0 * 3.0f * cu;
+    s_tmp[on + (unsigned)((kPF + i) * 64)] = wt(i) * CS2 * rho * si;
+    s_tmp[on + (unsigned)((kPH + i) * 64)] = (i == 0) ? 0.0f : wt(i) * etamu + wt(i) * (float)p0 * 3.0f * cu;
   }
-  phi[o] = p0;
-  P[o] = 0.0f;   // P0 = 0: the stored f are then f itself
-  J[o] = (float)p0 * ux;
-  J[g.ps + o] = (float)p0 * uy;
+  phi[(long long)y * g.pitch + x] = p0;
+  s0[on + (unsigned)(kPP * 64)] = 0.0f;   // P0 = 0: the stored f are then f itself
+  s0[on + (unsigned)(kPJ * 64)] = (float)p0 * ux;
+  s0[on + (unsigned)((kPJ + 1) * 64)] = (float)p0 * uy;
 }
 
 // Initial state, pass 2: place node-local populations in the stored (post-
 // collision) layout so that the pull of the first step returns them:
 // slot j at y holds the value of node y + c_j, or the opp(j) value of y itself
-// when y + c_j lies beyond a wall.
-__global__ __launch_bounds__(256) void k_init_unstream(const float* __restrict__ ft, const float* __restrict__ ht,
-                                                       float* __restrict__ f, float* __restrict__ h, Grid g, int wx,
-                                                       int wy) {
+// when y + c_j lies beyond a wall.  Slot 0 of h holds d0 = 0.
+__global__ __launch_bounds__(256) void k_init_unstream(const float* __restrict__ s_tmp, float* __restrict__ s0, Grid g,
+                                                       int wx, int wy) {
   const int x = blockIdx.x * 64 + (threadIdx.x & 63);
   const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (x >= g.nx || y >= g.ny) return;
-  const long long o = (long long)y * g.pitch + x;
+  const unsigned on = nbase(g, x, y);
 #pragma unroll
   for (int j = 0; j < 9; ++j) {
     int tx = x + cx(j), ty = y + cy(j);
     bool out = false;
     if (wx) out |= (tx < 0) | (tx >= g.nx); else tx = (tx + g.nx) % g.nx;
     if (wy) out |= (ty < 0) | (ty >= g.ny); else ty = (ty + g.ny) % g.ny;
-    long long src = out ? (long long)opp(j) * g.ps + o : (long long)j * g.ps + (long long)ty * g.pitch + tx;
-    f[(long long)j * g.ps + o] = ft[src];
-    h[(long long)j * g.ps + o] = (j == 0) ? 0.0f : ht[src];
+    const unsigned src = out ? on : nbase(g, tx, ty);
+    const int slot = out ? opp(j) : j;
+    s0[on + (unsigned)((kPF + j) * 64)] = s_tmp[src + (unsigned)((kPF + slot) * 64)];
+    s0[on + (unsigned)((kPH + j) * 64)] = (j == 0) ? 0.0f : s_tmp[src + (unsigned)((kPH + slot) * 64)];
   }
 }
 
@@ -905,25 +940,25 @@ hipError_t launch_moments(int form, const StepArgs& a, const MomentArgs& m, hipS
   return dispatch(form, a, m, true, s);
 }
 
-hipError_t launch_phi(const float* h, double* phi, const Grid& g, int wall_x, int wall_y, hipStream_t s) {
+hipError_t launch_phi(const float* snew, double* phi, const Grid& g, int wall_x, int wall_y, hipStream_t s) {
   const int nb = ((g.nx + kTX - 1) / kTX) * ((g.ny + kTY - 1) / kTY);
   dim3 grid((nb + kXcds - 1) / kXcds * kXcds);
   switch (wall_x | (wall_y << 1)) {
-    case 0: hipLaunchKernelGGL(k_phi<0>, grid, dim3(kFusedThreads), 0, s, h, phi, g); break;
-    case 1: hipLaunchKernelGGL(k_phi<1>, grid, dim3(kFusedThreads), 0, s, h, phi, g); break;
-    case 2: hipLaunchKernelGGL(k_phi<2>, grid, dim3(kFusedThreads), 0, s, h, phi, g); break;
-    default: hipLaunchKernelGGL(k_phi<3>, grid, dim3(kFusedThreads), 0, s, h, phi, g); break;
+    case 0: hipLaunchKernelGGL(k_phi<0>, grid, dim3(kFusedThreads), 0, s, snew, phi, g); break;
+    case 1: hipLaunchKernelGGL(k_phi<1>, grid, dim3(kFusedThreads), 0, s, snew, phi, g); break;
+    case 2: hipLaunchKernelGGL(k_phi<2>, grid, dim3(kFusedThreads), 0, s, snew, phi, g); break;
+    default: hipLaunchKernelGGL(k_phi<3>, grid, dim3(kFusedThreads), 0, s, snew, phi, g); break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_init(const float* phi0, const float* ux0, const float* uy0, float* f_tmp, float* h_tmp, float* f_out,
-                       float* h_out, float* J, double* phi, float* P, const Grid& g, const Phys& c, hipStream_t s) {
+hipError_t launch_init(const float* phi0, const float* ux0, const float* uy0, float* s_tmp, float* s0, double* phi,
+                       const Grid& g, const Phys& c, hipStream_t s) {
   dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4);
-  hipLaunchKernelGGL(k_init_local, grid, dim3(256), 0, s, phi0, ux0, uy0, f_tmp, h_tmp, J, phi, P, g, c);
+  hipLaunchKernelGGL(k_init_local, grid, dim3(256), 0, s, phi0, ux0, uy0, s_tmp, s0, phi, g, c);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_init_unstream, grid, dim3(256), 0, s, f_tmp, h_tmp, f_out, h_out, g, c.wall_x, c.wall_y);
+  hipLaunchKernelGGL(k_init_unstream, grid, dim3(256), 0, s, s_tmp, s0, g, c.wall_x, c.wall_y);
   return hipGetLastError();
 }
 
