@@ -95,7 +95,10 @@ def bench_batched(steps, loop_steps):
     phis = [np.asarray(x, np.float32) for _, _, x in insts]
     cells = sum(p["nx"] * p["ny"] for p in params)
     print(f"[bench] batched: 512 instances, {cells} nodes", file=sys.stderr, flush=True)
-    b = P.Batch(params, forms, phis)
+    tc = time.perf_counter()
+    b = P.Batch(params, forms, phis)   # includes timing the candidate launch shapes
+    create_s = time.perf_counter() - tc
+    shape = b.config
     b.step(16)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -121,7 +124,11 @@ def bench_batched(steps, loop_steps):
     loop = cells * loop_steps / el_loop / 1e6
     return {"MLUPS": round(batched, 1), "instances": 512, "nodes": cells, "steps": steps,
             "looping_plain_lbm_step_MLUPS": round(loop, 1), "loop_steps": loop_steps,
-            "speedup_vs_loop": round(batched / loop, 2), "unstable_instances": unstable}
+            "speedup_vs_loop": round(batched / loop, 2), "unstable_instances": unstable,
+            "launch_shape": {"one_kernel_per_form": bool(shape["split"]), "interior_path": bool(shape["fast"]),
+                             "workgroups_per_cu": shape["blocks_per_cu"] or "one per tile",
+                             "tuned_ms_per_step": round(shape["ms_per_step"], 4)},
+            "create_s_incl_tuning": round(create_s, 2)}
 
 
 def bench_adjoint(T):

@@ -150,8 +150,23 @@ int lbm_destroy(lbm_sim* sim);
  * array of `count` device pointers to each instance's nx*ny initial field.
  * ------------------------------------------------------------------------ */
 int lbm_batch_workspace_bytes(const lbm_params* params, int32_t count, size_t* bytes);
+/* Initialise every instance (as lbm_init, u0 = 0) and choose the launch
+ * shape of the batched step by timing the candidates on this batch (one
+ * fused kernel for every form or one per form; interior addressing on or
+ * off; persistent workgroups per CU or one per tile), unless a choice for
+ * the same instance sizes and forms is cached in this process or in the
+ * file named by PFLBM_TUNE_CACHE; PFLBM_BATCH_TUNE=0 skips the timing and
+ * PFLBM_BATCH_CFG=split,fast,blocks_per_cu forces a shape.  The
+ * timing steps run before the states are (re)initialised, so the returned
+ * batch starts from phi0 either way.  Synchronises `stream`. */
 int lbm_batch_create(lbm_batch** batch, const lbm_params* params, const int32_t* forms, int32_t count,
                      void* d_ws, size_t ws_bytes, const float* const* d_phi0, void* stream);
+/* The launch shape in use: split = 1 if the fused step runs one launch per
+ * force form, fast = 1 if interior tiles use the interior addressing path,
+ * blocks_per_cu = persistent workgroups per CU (0: one per tile), and the
+ * measured time per step in ms (0 when not timed).  Host-only. */
+int lbm_batch_config(const lbm_batch* batch, int32_t* split, int32_t* fast, int32_t* blocks_per_cu,
+                     double* ms_per_step);
 /* Advance every instance by nsteps (asynchronous). */
 int lbm_batch_step(lbm_batch* batch, int32_t nsteps, void* stream);
 /* Moments of instance k, same definitions and layout as lbm_moments. */

@@ -182,6 +182,13 @@ class Batch:
         check(lib().lbm_batch_status(self._h, flags, _stream(stream)))
         return [bool(v) for v in flags]
 
+    @property
+    def config(self):
+        """Launch shape chosen at creation: {split, fast, blocks_per_cu, ms_per_step}."""
+        sp, fa, bp, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
+        check(lib().lbm_batch_config(self._h, C.byref(sp), C.byref(fa), C.byref(bp), C.byref(ms)))
+        return {"split": sp.value, "fast": fa.value, "blocks_per_cu": bp.value, "ms_per_step": ms.value}
+
     def close(self):
         if getattr(self, "_h", None):
             lib().lbm_batch_destroy(self._h)

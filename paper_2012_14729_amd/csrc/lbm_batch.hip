@@ -4,13 +4,24 @@
 //   [instance descriptors][tile list][status ints][rho0 sums][partial sums]
 //   then, per instance, the same arrays as a single lattice (two interleaved
 //   state arrays, FP64 phi).
-// A step is two persistent launches over one tile list covering every
-// instance (sorted by force form): the fused collide-stream kernel and the
-// order-parameter kernel.  Steps are replayed from a HIP graph captured once
-// per batch in pairs (buffer A -> B -> A), so the host issues one graph
-// launch per kChunk steps.
+// A step is persistent launches over one tile list covering every instance
+// (sorted by force form): the fused collide-stream kernel (one launch for
+// every form, or one per form) and the order-parameter kernel.  Steps are
+// replayed from a HIP graph captured once per batch (buffer A -> B -> A ...),
+// so the host issues one graph launch per kChunk steps.
+//
+// Launch shapes are chosen by timing: at creation every candidate (one
+// kernel for all forms or one per form; interior addressing on or off;
+// persistent workgroups per CU, or one workgroup per tile) runs a few steps
+// on the batch itself, the fastest is kept, and the initial state is rebuilt.
+// Choices are cached per batch signature for the process, and in the file
+// named by PFLBM_TUNE_CACHE if set; PFLBM_BATCH_TUNE=0 skips the timing and
+// PFLBM_BATCH_CFG=split,fast,blocks_per_cu forces a shape (diagnostics).
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
+#include <map>
+#include <mutex>
 #include <cstdlib>
 #include <cstdarg>
 #include <cstdio>
@@ -49,6 +60,14 @@ struct BatchLayout {
   size_t desc, tiles, status, sums, partial, total;
   std::vector<InstLayout> inst;
   int ntiles;
+};
+
+// Launch shape of the batched step.
+struct BatchCfg {
+  int split;   // 1: one fused launch per force form; 0: one launch for every form
+  int fast;    // interior tiles may take the interior addressing path
+  int bpc;     // persistent workgroups per CU; 0: one workgroup per tile
+  double ms;   // measured time per step (ms), 0 if not timed
 };
 
 int ntiles_of(const lbm_params& p) { return ((p.nx + kTX - 1) / kTX) * ((p.ny + kTY - 1) / kTY); }
@@ -105,7 +124,9 @@ struct lbm_batch {
   std::vector<BatchInst> host;   // descriptors (as uploaded)
   int parity;                    // population buffer holding the current state
   int64_t step;
-  int nblocks;                   // persistent grid of the batched kernels
+  int cus;                       // compute units of the device
+  int form_beg[LBM_NUM_FORMS + 1];   // tile range of each force form in the sorted list
+  BatchCfg cfg;                  // launch shape in use
   hipStream_t cap;               // private stream used only for graph capture
   hipGraphExec_t exec;           // kChunk steps starting from parity 0
   BatchInst* d_inst() const { return (BatchInst*)(ws + L.desc); }
@@ -115,11 +136,26 @@ struct lbm_batch {
 
 namespace {
 
-int launch_pair_steps(lbm_batch* b, int nsteps, int parity0, hipStream_t st) {
+// Workgroups of a launch over n tiles: a multiple of the 8 XCDs.
+int grid_for(const lbm_batch* b, const BatchCfg& c, int n) {
+  const int want = c.bpc > 0 ? b->cus * c.bpc : n;
+  return std::max(8, (std::min(want, n) + 7) / 8 * 8);
+}
+
+int launch_pair_steps(lbm_batch* b, const BatchCfg& c, int nsteps, int parity0, hipStream_t st) {
   int par = parity0;
   for (int n = 0; n < nsteps; ++n) {
-    BHIP(launch_batch_fused(b->d_inst(), b->d_tiles(), b->L.ntiles, par, b->nblocks, st));
-    BHIP(launch_batch_phi(b->d_inst(), b->d_tiles(), b->L.ntiles, par, b->nblocks, st));
+    if (c.split) {
+      for (int f = 0; f < LBM_NUM_FORMS; ++f) {
+        const int t0 = b->form_beg[f], t1 = b->form_beg[f + 1];
+        if (t1 > t0)
+          BHIP(launch_batch_fused(b->d_inst(), b->d_tiles(), t0, t1, f, c.fast, par, grid_for(b, c, t1 - t0), st));
+      }
+    } else {
+      BHIP(launch_batch_fused(b->d_inst(), b->d_tiles(), 0, b->L.ntiles, -1, c.fast, par, grid_for(b, c, b->L.ntiles),
+                              st));
+    }
+    BHIP(launch_batch_phi(b->d_inst(), b->d_tiles(), b->L.ntiles, par, grid_for(b, c, b->L.ntiles), st));
     par = 1 - par;
   }
   return LBM_OK;
@@ -128,7 +164,7 @@ int launch_pair_steps(lbm_batch* b, int nsteps, int parity0, hipStream_t st) {
 int build_graph(lbm_batch* b) {
   BHIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
   BHIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-  const int r = launch_pair_steps(b, kChunk, 0, b->cap);
+  const int r = launch_pair_steps(b, b->cfg, kChunk, 0, b->cap);
   hipGraph_t graph = nullptr;
   const hipError_t e = hipStreamEndCapture(b->cap, &graph);
   if (r != LBM_OK) return r;
@@ -136,6 +172,135 @@ int build_graph(lbm_batch* b) {
   const hipError_t e2 = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (e2 != hipSuccess) return bfail(LBM_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e2));
+  return LBM_OK;
+}
+
+// Key of a batch for the tuning cache: device size, instance sizes, forms.
+uint64_t signature(const lbm_params* p, const int32_t* forms, int count, int cus) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) { h = (h ^ v) * 1099511628211ull; };
+  mix((uint64_t)cus);
+  mix((uint64_t)count);
+  for (int k = 0; k < count; ++k) {
+    mix((uint64_t)p[k].nx);
+    mix((uint64_t)p[k].ny);
+    mix((uint64_t)forms[k]);
+  }
+  return h;
+}
+
+std::mutex g_tune_mu;
+std::map<uint64_t, BatchCfg> g_tune;
+bool g_tune_file_read = false;
+
+const char* tune_file() { return std::getenv("PFLBM_TUNE_CACHE"); }
+
+void read_tune_file() {   // g_tune_mu held
+  if (g_tune_file_read) return;
+  g_tune_file_read = true;
+  const char* path = tune_file();
+  if (!path) return;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  unsigned long long key;
+  BatchCfg c{};
+  while (fscanf(f, "%llx %d %d %d %lf", &key, &c.split, &c.fast, &c.bpc, &c.ms) == 5) g_tune[(uint64_t)key] = c;
+  fclose(f);
+}
+
+void append_tune_file(uint64_t key, const BatchCfg& c) {   // g_tune_mu held
+  const char* path = tune_file();
+  if (!path) return;
+  if (FILE* f = fopen(path, "a")) {
+    fprintf(f, "%016llx %d %d %d %.6f\n", (unsigned long long)key, c.split, c.fast, c.bpc, c.ms);
+    fclose(f);
+  }
+}
+
+// Average time per step of configuration c (2 untimed steps, then 4).
+int time_cfg(lbm_batch* b, const BatchCfg& c, hipStream_t st, double* ms) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  BHIP(hipEventCreate(&e0));
+  const hipError_t ec = hipEventCreate(&e1);
+  int r = ec == hipSuccess ? LBM_OK : bfail(LBM_E_HIP, "hipEventCreate: %s", hipGetErrorString(ec));
+  if (r == LBM_OK) r = launch_pair_steps(b, c, 2, 0, st);
+  if (r == LBM_OK && hipEventRecord(e0, st) != hipSuccess) r = bfail(LBM_E_HIP, "hipEventRecord failed");
+  if (r == LBM_OK) r = launch_pair_steps(b, c, 4, 0, st);
+  if (r == LBM_OK && hipEventRecord(e1, st) != hipSuccess) r = bfail(LBM_E_HIP, "hipEventRecord failed");
+  float t = 0.f;
+  if (r == LBM_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+    r = bfail(LBM_E_HIP, "timing the batched step failed");
+  (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  *ms = t / 4.0;
+  return r;
+}
+
+// Initial states (Eqs. 31-32, reading A11) of every instance and clear flags.
+int init_states(lbm_batch* b, const lbm_params* params, const float* const* d_phi0, hipStream_t st, bool sums) {
+  char* ws = b->ws;
+  for (int k = 0; k < b->count; ++k) {
+    const InstLayout& I = b->L.inst[k];
+    const Phys c0 = derive_phys(&params[k], 0.0);
+    hipError_t e = launch_init(d_phi0[k], nullptr, nullptr, (float*)(ws + I.s[1]), (float*)(ws + I.s[0]),
+                               (double*)(ws + I.phi), I.g, c0, st);
+    if (e == hipSuccess && sums)   // sums of phi0 for rho0 (A12)
+      e = launch_phi_sum((double*)(ws + I.phi), I.g, (double*)(ws + b->L.partial) + (size_t)k * kPartials, kPartials,
+                         (double*)(ws + b->L.sums) + k, st);
+    if (e != hipSuccess) return bfail(LBM_E_HIP, "batch init: %s", hipGetErrorString(e));
+  }
+  if (launch_fill_int(b->d_status(), 0, b->count, st) != hipSuccess) return bfail(LBM_E_HIP, "status fill");
+  return LBM_OK;
+}
+
+// Pick the launch shape: cached, default, or the fastest candidate measured
+// on this batch (the timing steps change the state; it is rebuilt after).
+int choose_cfg(lbm_batch* b, const lbm_params* params, const int32_t* forms, const float* const* d_phi0,
+               hipStream_t st) {
+  const int occ = fused_blocks_per_cu();
+  const BatchCfg dflt{1, 1, occ, 0.0};
+  if (const char* fc = std::getenv("PFLBM_BATCH_CFG")) {   // forced shape "split,fast,blocks_per_cu"
+    BatchCfg c{0, 0, 0, 0.0};
+    if (sscanf(fc, "%d,%d,%d", &c.split, &c.fast, &c.bpc) != 3 || c.split < 0 || c.split > 1 || c.fast < 0 ||
+        c.fast > 1 || c.bpc < 0 || c.bpc > 64)
+      return bfail(LBM_E_INVAL, "PFLBM_BATCH_CFG must be split,fast,blocks_per_cu (0/1, 0/1, 0..64)");
+    b->cfg = c;
+    return LBM_OK;
+  }
+  const char* tv = std::getenv("PFLBM_BATCH_TUNE");
+  if (tv && tv[0] == '0') {
+    b->cfg = dflt;
+    return LBM_OK;
+  }
+  const uint64_t key = signature(params, forms, b->count, b->cus);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    read_tune_file();
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      b->cfg = it->second;
+      return LBM_OK;
+    }
+  }
+  BatchCfg best = dflt;
+  best.ms = 1e300;
+  for (int split = 0; split <= 1; ++split)
+    for (int fast = 0; fast <= 1; ++fast)
+      for (int bpc : {1, 2, 0}) {
+        if (bpc > occ) continue;
+        BatchCfg c{split, fast, bpc, 0.0};
+        double ms = 0.0;
+        if (int r = time_cfg(b, c, st, &ms)) return r;
+        if (ms < best.ms) {
+          best = c;
+          best.ms = ms;
+        }
+      }
+  if (int r = init_states(b, params, d_phi0, st, false)) return r;
+  b->cfg = best;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = best;
+  append_tune_file(key, best);
   return LBM_OK;
 }
 
@@ -182,18 +347,7 @@ int lbm_batch_create(lbm_batch** out, const lbm_params* params, const int32_t* f
     return code;
   };
   char* ws = b->ws;
-  // initial states (Eqs. 31-32, reading A11) and the sums of phi0 for rho0 (A12)
-  for (int k = 0; k < count; ++k) {
-    const InstLayout& I = b->L.inst[k];
-    const Phys c0 = derive_phys(&params[k], 0.0);
-    hipError_t e = launch_init(d_phi0[k], nullptr, nullptr, (float*)(ws + I.s[1]), (float*)(ws + I.s[0]),
-                               (double*)(ws + I.phi), I.g, c0, st);
-    if (e == hipSuccess)
-      e = launch_phi_sum((double*)(ws + I.phi), I.g, (double*)(ws + b->L.partial) + (size_t)k * kPartials, kPartials,
-                         (double*)(ws + b->L.sums) + k, st);
-    if (e != hipSuccess) return cleanup(bfail(LBM_E_HIP, "batch init: %s", hipGetErrorString(e)));
-  }
-  if (launch_fill_int(b->d_status(), 0, count, st) != hipSuccess) return cleanup(bfail(LBM_E_HIP, "status fill"));
+  if (int r = init_states(b, params, d_phi0, st, true)) return cleanup(r);
   std::vector<double> sums(count);
   if (hipMemcpyAsync(sums.data(), ws + b->L.sums, sizeof(double) * count, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
@@ -226,7 +380,9 @@ int lbm_batch_create(lbm_batch** out, const lbm_params* params, const int32_t* f
   std::stable_sort(order.begin(), order.end(), [&](int i, int j) { return forms[i] < forms[j]; });
   std::vector<TileRef> tiles;
   tiles.reserve(b->L.ntiles);
+  for (int f = 0; f <= LBM_NUM_FORMS; ++f) b->form_beg[f] = 0;
   for (int k : order) {
+    for (int f = forms[k] + 1; f <= LBM_NUM_FORMS; ++f) b->form_beg[f] += ntiles_of(params[k]);
     const int ntx = (params[k].nx + kTX - 1) / kTX, nty = (params[k].ny + kTY - 1) / kTY;
     for (int ty = 0; ty < nty; ++ty)
       for (int tx = 0; tx < ntx; ++tx) tiles.push_back(TileRef{k, tx, ty, 0});
@@ -241,7 +397,8 @@ int lbm_batch_create(lbm_batch** out, const lbm_params* params, const int32_t* f
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
                                               hipSuccess)
     return cleanup(bfail(LBM_E_HIP, "device query failed"));
-  b->nblocks = std::max(8, cus * fused_blocks_per_cu() / 8 * 8);
+  b->cus = cus;
+  if (int r = choose_cfg(b, params, forms, d_phi0, st)) return cleanup(r);
   if (int r = build_graph(b)) return cleanup(r);
   *out = b;
   return LBM_OK;
@@ -253,7 +410,7 @@ int lbm_batch_step(lbm_batch* b, int32_t nsteps, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   int n = nsteps;
   if (b->parity == 1 && n > 0) {   // realign to the graph's starting buffer
-    if (int r = launch_pair_steps(b, 1, 1, st)) return r;
+    if (int r = launch_pair_steps(b, b->cfg, 1, 1, st)) return r;
     b->parity = 0;
     --n;
   }
@@ -262,7 +419,7 @@ int lbm_batch_step(lbm_batch* b, int32_t nsteps, void* stream) {
     n -= kChunk;
   }
   if (n > 0) {
-    if (int r = launch_pair_steps(b, n, b->parity, st)) return r;
+    if (int r = launch_pair_steps(b, b->cfg, n, b->parity, st)) return r;
     b->parity = (b->parity + n) & 1;
   }
   b->step += nsteps;
@@ -283,6 +440,15 @@ int lbm_batch_status(lbm_batch* b, int32_t* h_flags, void* stream) {
   BHIP(hipMemcpyAsync(st.data(), b->d_status(), sizeof(int) * b->count, hipMemcpyDeviceToHost, (hipStream_t)stream));
   BHIP(hipStreamSynchronize((hipStream_t)stream));
   for (int k = 0; k < b->count; ++k) h_flags[k] = st[k] ? 1 : 0;
+  return LBM_OK;
+}
+
+int lbm_batch_config(const lbm_batch* b, int32_t* split, int32_t* fast, int32_t* blocks_per_cu, double* ms_per_step) {
+  if (!b || !split || !fast || !blocks_per_cu || !ms_per_step) return bfail(LBM_E_INVAL, "NULL argument");
+  *split = b->cfg.split;
+  *fast = b->cfg.fast;
+  *blocks_per_cu = b->cfg.bpc;
+  *ms_per_step = b->cfg.ms;
   return LBM_OK;
 }
 

@@ -127,9 +127,10 @@ hipError_t launch_init(const float* phi0, const float* ux0, const float* uy0, fl
 hipError_t launch_phi_sum(const double* phi, const Grid& g, double* partial, int npartial, double* out,
                           hipStream_t s);
 hipError_t launch_fill_int(int* p, int value, int n, hipStream_t s);
-// persistent batched step kernels over a tile list (periodic instances)
-hipError_t launch_batch_fused(const BatchInst* inst, const TileRef* tiles, int ntiles, int parity, int nblocks,
-                              hipStream_t s);
+// persistent batched step kernels over a tile list (periodic instances); form < 0:
+// one kernel for every form, else the tiles [t0, t1) all have that form
+hipError_t launch_batch_fused(const BatchInst* inst, const TileRef* tiles, int t0, int t1, int form, int fast,
+                              int parity, int nblocks, hipStream_t s);
 hipError_t launch_batch_phi(const BatchInst* inst, const TileRef* tiles, int ntiles, int parity, int nblocks,
                             hipStream_t s);
 int fused_blocks_per_cu();

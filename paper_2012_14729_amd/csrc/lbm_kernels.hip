@@ -92,17 +92,21 @@ __device__ __forceinline__ T* at(T* base, unsigned boff) {
 __device__ __forceinline__ float ld_nt(const float* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ void st_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
 
-// Byte offsets, from an interior tile's input origin (plane 0 of node
-// (x0 - 64, y0 - 2)), of plane 0 of the nodes (xr - 1 + k, yr), k = 0, 1, 2,
-// where (xr, yr) is relative to the tile corner (x0, y0).  A pull of
-// direction I by node (xr, yr) reads v3[1 - c_Ix] from the origin moved by
-// -c_Iy rows.
-__device__ __forceinline__ void node_offsets(const Grid& g, int xr, int yr, unsigned* v3) {
-  const int row = (yr + 2) * g.rowe;
+// Interior tiles address a state array from an origin at plane 0 of node
+// (xo, y0 - 2), xo = the first node of the 64-node row segment holding
+// x0 - 2 (the leftmost column any pull of the tile reads).
+__device__ __forceinline__ int tile_xo(int x0) { return (x0 - 2) & ~63; }
+
+// Byte offsets, from an interior tile's input origin, of plane 0 of the
+// nodes (x0 + xr - 1 + k, y0 + yr), k = 0, 1, 2.  A pull of direction I by
+// node (x0 + xr, y0 + yr) reads v3[1 - c_Ix] from the origin moved by -c_Iy
+// rows.
+__device__ __forceinline__ void node_offsets(const Grid& g, int x0, int xr, int yr, unsigned* v3) {
+  const int row = (yr + 2) * g.rowe, s0 = tile_xo(x0) >> 6;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const int xs = xr + k - 1;
-    v3[k] = 4u * (unsigned)(row + ((xs >> 6) + 1) * kSegE + (xs & 63));
+    const int X = x0 + xr + k - 1;
+    v3[k] = 4u * (unsigned)(row + ((X >> 6) - s0) * kSegE + (X & 63));
   }
 }
 
@@ -464,13 +468,13 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
   const int uy_ = ty + 1, ux_ = lx + 1;             // velocity-ring coordinates of this node
   int x, y;
   bool valid, act;
-  const float* tin = nullptr;   // interior tiles: input origin (node (x0 - 64, y0 - 2))
+  const float* tin = nullptr;   // interior tiles: input origin (node (tile_xo(x0), y0 - 2))
   float* tout = nullptr;        // interior tiles: output origin (node (x0, y0))
   if constexpr (FAST) {
     x = x0 + lx;
     y = y0 + ty;
     valid = act = true;
-    tin = a.sin + nbase(g, x0 - 64, y0 - 2);
+    tin = a.sin + nbase(g, tile_xo(x0), y0 - 2);
     tout = a.sout + nbase(g, x0, y0);
   } else {
     valid = ring_global<WX, WY>(uy_, ux_, x0, y0, a, x, y);
@@ -511,7 +515,7 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
       bool ok = true;
       if constexpr (FAST) {
         unsigned rv[3];
-        node_offsets(g, rux - 1, ruy - 1, rv);
+        node_offsets(g, x0, rux - 1, ruy - 1, rv);
         load_fp_tile<false>(tin, g.rowe, rv, rft, rps);
       } else {
         int rx, ry;
@@ -529,7 +533,7 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
   }
   NodeState n;
   unsigned v3[3] = {0u, 0u, 0u};
-  if constexpr (FAST) node_offsets(g, lx, ty, v3);
+  if constexpr (FAST) node_offsets(g, x0, lx, ty, v3);
   if (valid) {
     if constexpr (FAST) load_fp_tile<true>(tin, g.rowe, v3, ft, ps);
     else load_fp<WX, WY>(a, x, y, ft, ps);
@@ -717,9 +721,9 @@ __device__ __forceinline__ void phi_tile_impl(const float* __restrict__ snew, do
   if (x >= g.nx || y >= g.ny) return;
   double sum;
   if constexpr (FAST) {
-    const float* tin = snew + nbase(g, tile_x * kTX - 64, tile_y * kTY - 2);
+    const float* tin = snew + nbase(g, tile_xo(tile_x * kTX), tile_y * kTY - 2);
     unsigned v3[3];
-    node_offsets(g, lx, ty, v3);
+    node_offsets(g, tile_x * kTX, lx, ty, v3);
     sum = (double)pull_tile<0, kPH, true>(tin, g.rowe, v3);
     sum += (double)pull_tile<1, kPH + 1, true>(tin, g.rowe, v3);
     sum += (double)pull_tile<2, kPH + 2, true>(tin, g.rowe, v3);
@@ -757,45 +761,61 @@ __global__ __launch_bounds__(kFusedThreads) void k_phi(const float* __restrict__
 }
 
 // Batched step: persistent workgroups walk a tile list covering every
-// instance (sorted by force form, then instance).  The list is cut into 8
-// contiguous bands, one per XCD; the workgroups of an XCD stride through its
-// band, so consecutive tiles of an instance share that XCD's L2.
-__device__ __forceinline__ void band(int ntiles, int& beg, int& end, int& first, int& stride) {
-  const int per = (ntiles + kXcds - 1) / kXcds;
-  const int xcd = blockIdx.x % kXcds;
-  beg = xcd * per;
-  end = min(ntiles, beg + per);
-  first = beg + blockIdx.x / kXcds;
-  stride = gridDim.x / kXcds;
+// instance (sorted by force form, then instance).  A launch covers the tile
+// range [t0, t1), cut into 8 contiguous bands, one per XCD; the workgroups of
+// an XCD stride through its band, so consecutive tiles of an instance share
+// that XCD's L2.
+__device__ __forceinline__ void band(int t0, int t1, int& first, int& end, int& stride) {
+  const int per = (t1 - t0 + kXcds - 1) / kXcds;
+  const int beg = t0 + (int)(blockIdx.x % kXcds) * per;
+  end = min(t1, beg + per);
+  first = beg + (int)(blockIdx.x / kXcds);
+  stride = (int)(gridDim.x / kXcds);
 }
 
+// One tile of instance descriptor bi: FAST_OK lets interior tiles take the
+// interior addressing path (more registers); otherwise every tile takes the
+// general one.
+template <int FORM, bool FAST_OK>
+__device__ __forceinline__ void batch_tile(Lds& s, const StepArgs& a, int tx, int ty) {
+  if constexpr (FAST_OK) fused_tile<FORM, false, 0>(s, a, MomentArgs{}, tx, ty);
+  else tile_impl<FORM, false, 0, false>(s, a, MomentArgs{}, tx, ty);
+}
+
+// FORM >= 0: every tile of [t0, t1) has that force form (the tile list is
+// sorted by form); FORM < 0: any form, dispatched per tile.
+template <int FORM, bool FAST_OK>
 __global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_fused(
-    const BatchInst* __restrict__ inst, const TileRef* __restrict__ tiles, int ntiles, int parity) {
+    const BatchInst* __restrict__ inst, const TileRef* __restrict__ tiles, int t0, int t1, int parity) {
   __shared__ Lds s;
-  int beg, end, first, stride;
-  band(ntiles, beg, end, first, stride);
+  int first, end, stride;
+  band(t0, t1, first, end, stride);
   for (int t = first; t < end; t += stride) {
     const TileRef tr = tiles[t];
     const BatchInst& bi = inst[tr.inst];
     __syncthreads();   // the previous tile is done with the LDS
     const StepArgs& a = bi.a[parity];
-    switch (bi.form) {
-      case 0: fused_tile<0, false, 0>(s, a, MomentArgs{}, tr.tx, tr.ty); break;
-      case 1: fused_tile<1, false, 0>(s, a, MomentArgs{}, tr.tx, tr.ty); break;
-      case 2: fused_tile<2, false, 0>(s, a, MomentArgs{}, tr.tx, tr.ty); break;
-      case 3: fused_tile<3, false, 0>(s, a, MomentArgs{}, tr.tx, tr.ty); break;
-      case 4: fused_tile<4, false, 0>(s, a, MomentArgs{}, tr.tx, tr.ty); break;
-      case 5: fused_tile<5, false, 0>(s, a, MomentArgs{}, tr.tx, tr.ty); break;
-      case 6: fused_tile<6, false, 0>(s, a, MomentArgs{}, tr.tx, tr.ty); break;
-      default: fused_tile<7, false, 0>(s, a, MomentArgs{}, tr.tx, tr.ty); break;
+    if constexpr (FORM >= 0) {
+      batch_tile<FORM, FAST_OK>(s, a, tr.tx, tr.ty);
+    } else {
+      switch (bi.form) {
+        case 0: batch_tile<0, FAST_OK>(s, a, tr.tx, tr.ty); break;
+        case 1: batch_tile<1, FAST_OK>(s, a, tr.tx, tr.ty); break;
+        case 2: batch_tile<2, FAST_OK>(s, a, tr.tx, tr.ty); break;
+        case 3: batch_tile<3, FAST_OK>(s, a, tr.tx, tr.ty); break;
+        case 4: batch_tile<4, FAST_OK>(s, a, tr.tx, tr.ty); break;
+        case 5: batch_tile<5, FAST_OK>(s, a, tr.tx, tr.ty); break;
+        case 6: batch_tile<6, FAST_OK>(s, a, tr.tx, tr.ty); break;
+        default: batch_tile<7, FAST_OK>(s, a, tr.tx, tr.ty); break;
+      }
     }
   }
 }
 
 __global__ __launch_bounds__(kFusedThreads) void k_batch_phi(const BatchInst* __restrict__ inst,
                                                              const TileRef* __restrict__ tiles, int ntiles, int parity) {
-  int beg, end, first, stride;
-  band(ntiles, beg, end, first, stride);
+  int first, end, stride;
+  band(0, ntiles, first, end, stride);
   for (int t = first; t < end; t += stride) {
     const TileRef tr = tiles[t];
     const StepArgs& a = inst[tr.inst].a[parity];
@@ -979,9 +999,27 @@ hipError_t launch_fill_int(int* p, int value, int n, hipStream_t s) {
 
 namespace pflbm {
 
-hipError_t launch_batch_fused(const BatchInst* inst, const TileRef* tiles, int ntiles, int parity, int nblocks,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_fused, dim3(nblocks), dim3(kFusedThreads), 0, s, inst, tiles, ntiles, parity);
+template <int FORM>
+void launch_batch_form(bool fast, dim3 grid, hipStream_t s, const BatchInst* inst, const TileRef* tiles, int t0,
+                       int t1, int parity) {
+  if (fast) hipLaunchKernelGGL((k_batch_fused<FORM, true>), grid, dim3(kFusedThreads), 0, s, inst, tiles, t0, t1, parity);
+  else hipLaunchKernelGGL((k_batch_fused<FORM, false>), grid, dim3(kFusedThreads), 0, s, inst, tiles, t0, t1, parity);
+}
+
+hipError_t launch_batch_fused(const BatchInst* inst, const TileRef* tiles, int t0, int t1, int form, int fast,
+                              int parity, int nblocks, hipStream_t s) {
+  const dim3 grid(nblocks);
+  switch (form) {
+    case 0: launch_batch_form<0>(fast, grid, s, inst, tiles, t0, t1, parity); break;
+    case 1: launch_batch_form<1>(fast, grid, s, inst, tiles, t0, t1, parity); break;
+    case 2: launch_batch_form<2>(fast, grid, s, inst, tiles, t0, t1, parity); break;
+    case 3: launch_batch_form<3>(fast, grid, s, inst, tiles, t0, t1, parity); break;
+    case 4: launch_batch_form<4>(fast, grid, s, inst, tiles, t0, t1, parity); break;
+    case 5: launch_batch_form<5>(fast, grid, s, inst, tiles, t0, t1, parity); break;
+    case 6: launch_batch_form<6>(fast, grid, s, inst, tiles, t0, t1, parity); break;
+    case 7: launch_batch_form<7>(fast, grid, s, inst, tiles, t0, t1, parity); break;
+    default: launch_batch_form<-1>(fast, grid, s, inst, tiles, t0, t1, parity); break;
+  }
   return hipGetLastError();
 }
 
@@ -991,10 +1029,12 @@ hipError_t launch_batch_phi(const BatchInst* inst, const TileRef* tiles, int nti
   return hipGetLastError();
 }
 
-// Resident 512-thread workgroups per CU of the batched step kernel.
+// Resident workgroups per CU of the batched step kernel (the any-form
+// kernel with the interior path, the largest register footprint).
 int fused_blocks_per_cu() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_fused, kFusedThreads, 0) != hipSuccess || n < 1) n = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_fused<-1, true>, kFusedThreads, 0) != hipSuccess || n < 1)
+    n = 1;
   return n;
 }
 

@@ -67,3 +67,61 @@ def test_batch_flags_only_the_diverged_instance():
     b = P.Batch([p.as_dict() for p in params], forms, phis)
     b.step(20)
     assert b.status() == [False, False, True, False, False]
+
+
+def wide_batch():
+    """Instances wide enough to hold interior tiles (sides 96..256), all eight forms."""
+    sides = (96, 160, 192, 256, 128, 224, 144, 200)
+    params, phis = [], []
+    for k, s in enumerate(sides):
+        params.append(WL.ParamSet(nx=s, ny=s // 2 + 8 * (k % 3), rho1=(1.0, 10.0, 100.0)[k % 3], rho2=1.0, nu1=0.1,
+                                  nu2=0.1, sigma=3e-3, W=4.0, M=0.1, tau_h=0.8))
+        phis.append(np.asarray(WL.two_droplets(params[-1].nx, params[-1].ny, s / 8, s / 10, 2.0, 4.0), np.float32))
+    return params, list(range(8)), phis
+
+
+@pytest.mark.parametrize("cfg", ["0,0,1", "0,1,1", "0,0,2", "0,1,2", "0,1,0", "1,0,1", "1,1,1", "1,0,2",
+                                 "1,1,2", "1,0,0", "1,1,0", "0,0,0"])
+def test_every_launch_shape_matches_single_lattice(cfg, monkeypatch):
+    """Whatever launch shape the tuner picks (one kernel or one per form,
+    interior addressing on or off, persistent or one workgroup per tile), the
+    instances evolve bit for bit as single lattices."""
+    import paper_2012_14729_amd as P
+    params, forms, phis = wide_batch()
+    monkeypatch.setenv("PFLBM_BATCH_CFG", cfg)
+    b = P.Batch([p.as_dict() for p in params], forms, phis)
+    assert b.config["split"] == int(cfg[0]) and b.config["fast"] == int(cfg[2])
+    b.step(23)
+    torch.cuda.synchronize()
+    assert not any(b.status())
+    for k, (p, f, phi) in enumerate(zip(params, forms, phis)):
+        s = P.Simulation(p.as_dict(), phi)
+        s.step(23, P.FORMS[f])
+        ms, mb = s.moments(P.FORMS[f]), b.moments(k)
+        for key in ("phi", "rho", "ux", "uy", "P"):
+            assert torch.equal(ms[key], mb[key]), (cfg, k, key)
+
+
+def test_tuned_batch_starts_from_phi0(monkeypatch):
+    """Creation times the candidate launch shapes by stepping the batch and
+    then rebuilds the initial state: a tuned batch and an untuned one give
+    identical states."""
+    import paper_2012_14729_amd as P
+    params, forms, phis = wide_batch()
+    params = params[:5]
+    forms, phis = forms[:5], phis[:5]
+    monkeypatch.delenv("PFLBM_BATCH_CFG", raising=False)
+    monkeypatch.delenv("PFLBM_BATCH_TUNE", raising=False)
+    tuned = P.Batch([p.as_dict() for p in params], forms, phis)
+    cfg = tuned.config
+    print(f"[batch] tuned shape {cfg}", flush=True)
+    assert cfg["ms_per_step"] > 0 and cfg["split"] in (0, 1) and cfg["fast"] in (0, 1) and cfg["blocks_per_cu"] >= 0
+    monkeypatch.setenv("PFLBM_BATCH_TUNE", "0")
+    plain = P.Batch([p.as_dict() for p in params], forms, phis)
+    for b in (tuned, plain):
+        b.step(12)
+    torch.cuda.synchronize()
+    for k in range(len(params)):
+        mt, mp = tuned.moments(k), plain.moments(k)
+        for key in ("phi", "rho", "ux", "uy", "P"):
+            assert torch.equal(mt[key], mp[key]), (k, key)
