@@ -483,9 +483,21 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
   const unsigned on = nbase(g, x, y);   // general path: plane 0 of this node (valid nodes)
 
   // This node's flow populations are pulled after the ring velocities (the
-  // ring threads would otherwise hold both sets of registers at once).
+  // ring threads would otherwise hold both sets of registers at once).  On
+  // interior tiles the ring threads request their ring node's populations
+  // first, so they arrive while the order parameter is staged.
   float ft[9], ps[9], h[9];
   float j0 = 0.f, j1 = 0.f;
+  float rft[9], rps[9];
+  int ruy = 0, rux = 0;
+  if constexpr (FAST && !MOMENTS) {
+    if (tid < NRING) {
+      ring_pos(tid, ruy, rux);
+      unsigned rv[3];
+      node_offsets(g, x0, rux - 1, ruy - 1, rv);
+      load_fp_tile<false>(tin, g.rowe, rv, rft, rps);
+    }
+  }
   // Stage A: phi tile with a 3-node halo (periodic wrap / even reflection at walls, Sec. IV)
   if constexpr (FAST) {
     const double* tphi = a.phi + ((long long)(y0 - 3) * g.pitch + (x0 - 3));
@@ -509,15 +521,9 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
   // Stage C: velocities of the ring (step only), then of this node.
   if constexpr (!MOMENTS) {
     if (tid < NRING) {
-      int ruy, rux;
-      ring_pos(tid, ruy, rux);
-      float rft[9], rps[9];
       bool ok = true;
-      if constexpr (FAST) {
-        unsigned rv[3];
-        node_offsets(g, x0, rux - 1, ruy - 1, rv);
-        load_fp_tile<false>(tin, g.rowe, rv, rft, rps);
-      } else {
+      if constexpr (!FAST) {
+        ring_pos(tid, ruy, rux);
         int rx, ry;
         ok = ring_global<WX, WY>(ruy, rux, x0, y0, a, rx, ry);
         if (ok) load_fp<WX, WY>(a, rx, ry, rft, rps);
