@@ -518,7 +518,14 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
   stage_b<FORM>(s, tid, c);
   __syncthreads();
 
-  // Stage C: velocities of the ring (step only), then of this node.
+  // Stage C: velocities of the ring (step only), then of this node.  On
+  // interior tiles this node's pulls are issued first for the CPF and PF
+  // forms, so their latency overlaps the ring's work (measured: no gain for
+  // the CSF forms, and the stress forms need those registers for the ring).
+  constexpr bool kEarlyOwn = FAST && FORM >= 2 && FORM <= 5;
+  unsigned v3[3] = {0u, 0u, 0u};
+  if constexpr (FAST) node_offsets(g, x0, lx, ty, v3);
+  if constexpr (kEarlyOwn) load_fp_tile<true>(tin, g.rowe, v3, ft, ps);
   if constexpr (!MOMENTS) {
     if (tid < NRING) {
       bool ok = true;
@@ -538,11 +545,9 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
     }
   }
   NodeState n;
-  unsigned v3[3] = {0u, 0u, 0u};
-  if constexpr (FAST) node_offsets(g, x0, lx, ty, v3);
   if (valid) {
-    if constexpr (FAST) load_fp_tile<true>(tin, g.rowe, v3, ft, ps);
-    else load_fp<WX, WY>(a, x, y, ft, ps);
+    if constexpr (!FAST) load_fp<WX, WY>(a, x, y, ft, ps);
+    else if constexpr (!kEarlyOwn) load_fp_tile<true>(tin, g.rowe, v3, ft, ps);
     velocity_from<FORM, true>(s, a, uy_, ux_, ft, ps, n);
     if constexpr (!MOMENTS) {
       const double ph = s.phi[uy_ + 2][ux_ + 2];
