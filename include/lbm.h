@@ -202,6 +202,10 @@ int lbm_adjoint_seed_phi_misfit(lbm_adj* adj, const float* d_target, double* d_l
  * (in place): lambda_t = (ds_{t+1}/ds_t)^T lambda_{t+1}.  Adds this step's
  * contributions to dL/dsigma and dL/dM (Eqs. 6, 29-37, 41-43). */
 int lbm_adjoint_step(lbm_adj* adj, int32_t force_form, double* d_lambda, void* stream);
+/* The same step linearised about the state held in d_blob (written by
+ * lbm_save of this adjoint's simulation) instead of the simulation's current
+ * state; the simulation is not touched. */
+int lbm_adjoint_step_blob(lbm_adj* adj, const void* d_blob, int32_t force_form, double* d_lambda, void* stream);
 /* Adjoint of lbm_init (reading A11): dL/dphi0 (nx*ny FP64) from lambda_0,
  * adding the initial state's contributions to dL/dsigma and dL/dM.  phi0,
  * u0 as given to lbm_init. */

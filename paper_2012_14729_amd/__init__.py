@@ -231,6 +231,16 @@ class Adjoint:
         check(lib().lbm_adjoint_step(self._h, form_index(form), _ptr(lam), _stream(stream)))
         return lam
 
+    def step_blob(self, blob, lam, form, stream=None):
+        """Adjoint step about the state in `blob` (a Simulation.save() of this
+        adjoint's simulation)."""
+        check_lambda(lam, self.sim.ny, self.sim.nx, self.workspace.device)
+        if not (torch.is_tensor(blob) and blob.dtype == torch.uint8 and blob.numel() == self.sim.state_bytes()
+                and blob.device == self.workspace.device):
+            raise ValueError("blob must be a uint8 tensor from Simulation.save() on the same device")
+        check(lib().lbm_adjoint_step_blob(self._h, _ptr(blob), form_index(form), _ptr(lam), _stream(stream)))
+        return lam
+
     def init(self, lam, phi0, ux0=None, uy0=None, stream=None):
         dev = self.workspace.device
         check_lambda(lam, self.sim.ny, self.sim.nx, dev)
@@ -299,8 +309,7 @@ def adjoint_gradients(params, form, T, phi0, target, ux0=None, uy0=None, every=N
             if t < t_hi - 1:
                 sim.step(1, form)
         for t in reversed(range(t_lo, t_hi)):
-            sim.restore(states[t - t_lo])
-            adj.step(lam, form)
+            adj.step_blob(states[t - t_lo], lam, form)
         del states
     dphi0 = adj.init(lam, phi0, ux0, uy0)
     dsig, dM = adj.param_grads()

@@ -271,7 +271,8 @@ __global__ void k_adj_fe(AGrid g, ABuf b) {   // D = div(phi u) (Eq. 41), dQ = Q
 // Streaming and both collisions transposed (Eqs. 29-36, 43), node-local.
 // lam: lambda_{n+1} (9 f, 9 h, 2 J planes).  Writes the partial adjoints of
 // the pre-collision populations and of every node quantity they depend on.
-__global__ void k_adj_b1(AGrid g, ACon c, ABuf b, const double* __restrict__ lam, double* __restrict__ lam_out) {
+// lam and lam_out may be the same array (in-place step): not restrict-qualified.
+__global__ void k_adj_b1(AGrid g, ACon c, ABuf b, const double* lam, double* lam_out) {
   const int N = g.nx * g.ny;
   const int k = blockIdx.x * kB + threadIdx.x;
   if (k >= N) return;
@@ -701,7 +702,6 @@ struct lbm_adj {
   ACon c;
   ABuf b;
   char* ws;
-  double* lam_tmp;
   double* red;   // two doubles + loss
   double* lossd;
 };
@@ -717,9 +717,9 @@ size_t adj_doubles(const lbm_params* p) {
   const size_t N = (size_t)p->nx * p->ny, N1 = (size_t)(p->nx + 2) * (p->ny + 2),
                N2 = (size_t)(p->nx + 4) * (p->ny + 4);
   // interior planes: f9 h9 J2 phi Fsf2 F2 rho muv tauf u2 gr2 P Q2 D dQ2 divn lf9 lh9 lP lrho lu2 lF2 lgr2 lphi lD lQ2
-  //                  lmun lossd + lam_tmp 20
+  //                  lmun lossd
   const size_t nin = 9 + 9 + 2 + 1 + 2 + 2 + 1 + 1 + 1 + 2 + 2 + 1 + 2 + 1 + 2 + 1 + 9 + 9 + 1 + 1 + 2 + 2 + 2 + 1 +
-                     1 + 2 + 1 + 1 + 20;
+                     1 + 2 + 1 + 1;
   // e1 planes: G1 2, L1, mu1, T1 3, n1 2, s1, ue1 2, Q1 2, lue1 2, lphie1, lG1 2, lL1, gsig, gM
   const size_t ne1 = 2 + 1 + 1 + 3 + 2 + 1 + 2 + 2 + 2 + 1 + 2 + 1 + 1 + 1;
   // e2 planes: phie2, lphie2
@@ -777,7 +777,6 @@ int lbm_adjoint_create(lbm_adj** out, lbm_sim* sim, void* d_ws, size_t ws_bytes)
   b.lf = take(9 * N); b.lh = take(9 * N); b.lP = take(N); b.lrho = take(N); b.lu = take(2 * N); b.lF = take(2 * N);
   b.lgr = take(2 * N); b.lphi = take(N); b.lD = take(N); b.lQ = take(2 * N); b.lmun = take(N);
   a->lossd = take(N);
-  a->lam_tmp = take(20 * N);
   b.G1 = take(2 * N1); b.L1 = take(N1); b.mu1 = take(N1); b.T1 = take(3 * N1); b.n1 = take(2 * N1); b.s1 = take(N1);
   b.ue1 = take(2 * N1); b.Q1 = take(2 * N1); b.lue1 = take(2 * N1); b.lphie1 = take(N1);
   b.lG1 = take(2 * N1); b.lL1 = take(N1); b.gsig = take(N1); b.gM = take(N1);
@@ -815,31 +814,51 @@ int lbm_adjoint_seed_phi_misfit(lbm_adj* a, const float* d_target, double* d_lam
   return e == hipSuccess ? LBM_OK : set_error(LBM_E_HIP, "adjoint seed: %s", hipGetErrorString(e));
 }
 
-int lbm_adjoint_step(lbm_adj* a, int32_t form, double* d_lambda, void* stream) {
-  if (!a || !d_lambda) return set_error(LBM_E_INVAL, "NULL argument");
-  if (form < 0 || form >= LBM_NUM_FORMS) return set_error(LBM_E_INVAL, "bad force form %d", form);
-  hipStream_t st = (hipStream_t)stream;
+namespace {
+
+// One adjoint step linearised about the state (S, phi).  lambda is updated in
+// place: k_adj_b1 is the only reader of its planes 0-17 (at neighbouring
+// nodes) and reads planes 18-19 of its own node before writing them;
+// k_adj_b7 writes planes 0-17 after b1 has finished.
+int adjoint_step_at(lbm_adj* a, const float* S, const double* phis, int32_t form, double* d_lambda, hipStream_t st) {
   a->c.form = form;
   const AGrid& g = a->g;
   const long long N = (long long)g.nx * g.ny, N1 = (long long)(g.nx + 2) * (g.ny + 2),
                   N2 = (long long)(g.nx + 4) * (g.ny + 4);
-  SimView v;
-  if (int r = sim_view(a->sim, &v)) return r;
-  hipLaunchKernelGGL(k_adj_unpack, dim3(nblk(N)), dim3(kB), 0, st, v.s, v.phi, g, a->b);
+  hipLaunchKernelGGL(k_adj_unpack, dim3(nblk(N)), dim3(kB), 0, st, S, phis, g, a->b);
   hipLaunchKernelGGL(k_adj_fa, dim3(nblk(N2)), dim3(kB), 0, st, g, a->b);
   hipLaunchKernelGGL(k_adj_fb, dim3(nblk(N1)), dim3(kB), 0, st, g, a->c, a->b);
   hipLaunchKernelGGL(k_adj_fc, dim3(nblk(N)), dim3(kB), 0, st, g, a->c, a->b);
   hipLaunchKernelGGL(k_adj_fd, dim3(nblk(N1)), dim3(kB), 0, st, g, a->c, a->b);
   hipLaunchKernelGGL(k_adj_fe, dim3(nblk(N)), dim3(kB), 0, st, g, a->b);
-  hipLaunchKernelGGL(k_adj_b1, dim3(nblk(N)), dim3(kB), 0, st, g, a->c, a->b, d_lambda, a->lam_tmp);
+  hipLaunchKernelGGL(k_adj_b1, dim3(nblk(N)), dim3(kB), 0, st, g, a->c, a->b, d_lambda, d_lambda);
   hipLaunchKernelGGL(k_adj_b2, dim3(nblk(N1)), dim3(kB), 0, st, g, a->b);
   hipLaunchKernelGGL(k_adj_b3, dim3(nblk(N)), dim3(kB), 0, st, g, a->c, a->b);
   hipLaunchKernelGGL(k_adj_b4, dim3(nblk(N1)), dim3(kB), 0, st, g, a->c, a->b);
   hipLaunchKernelGGL(k_adj_b6, dim3(nblk(N2)), dim3(kB), 0, st, g, a->b);
-  hipLaunchKernelGGL(k_adj_b7, dim3(nblk(N)), dim3(kB), 0, st, g, a->b, a->lam_tmp);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess) e = hipMemcpyAsync(d_lambda, a->lam_tmp, sizeof(double) * 20 * N, hipMemcpyDeviceToDevice, st);
+  hipLaunchKernelGGL(k_adj_b7, dim3(nblk(N)), dim3(kB), 0, st, g, a->b, d_lambda);
+  const hipError_t e = hipGetLastError();
   return e == hipSuccess ? LBM_OK : set_error(LBM_E_HIP, "adjoint step: %s", hipGetErrorString(e));
+}
+
+}  // namespace
+
+int lbm_adjoint_step(lbm_adj* a, int32_t form, double* d_lambda, void* stream) {
+  if (!a || !d_lambda) return set_error(LBM_E_INVAL, "NULL argument");
+  if (form < 0 || form >= LBM_NUM_FORMS) return set_error(LBM_E_INVAL, "bad force form %d", form);
+  SimView v;
+  if (int r = sim_view(a->sim, &v)) return r;
+  return adjoint_step_at(a, v.s, v.phi, form, d_lambda, (hipStream_t)stream);
+}
+
+int lbm_adjoint_step_blob(lbm_adj* a, const void* d_blob, int32_t form, double* d_lambda, void* stream) {
+  if (!a || !d_blob || !d_lambda) return set_error(LBM_E_INVAL, "NULL argument");
+  if (form < 0 || form >= LBM_NUM_FORMS) return set_error(LBM_E_INVAL, "bad force form %d", form);
+  SimView v;
+  if (int r = sim_view(a->sim, &v)) return r;
+  const char* b = (const char*)d_blob;   // lbm_save layout: state array, then phi
+  const size_t sb = (size_t)kNPL * (size_t)v.g.ps * sizeof(float);
+  return adjoint_step_at(a, (const float*)b, (const double*)(b + sb), form, d_lambda, (hipStream_t)stream);
 }
 
 int lbm_adjoint_init(lbm_adj* a, const float* d_phi0, const float* d_ux0, const float* d_uy0, const double* d_lambda0,

@@ -352,26 +352,24 @@ int lbm_state_bytes(const lbm_sim* s, size_t* bytes) {
 
 int lbm_save(lbm_sim* s, void* d_blob, void* stream) {
   if (!s || !d_blob) return fail(LBM_E_INVAL, "NULL argument");
-  hipStream_t st = (hipStream_t)stream;
   const size_t sb = s->state_floats() * sizeof(float), pb = (size_t)s->L.g.ps * sizeof(double);
   char* b = (char*)d_blob;
-  HIPCHK(hipMemcpyAsync(b, s->S(s->cur), sb, hipMemcpyDeviceToDevice, st));
-  HIPCHK(hipMemcpyAsync(b + sb, s->phi(), pb, hipMemcpyDeviceToDevice, st));
-  HIPCHK(hipMemcpyAsync(b + sb + pb, s->status(), sizeof(int), hipMemcpyDeviceToDevice, st));
+  const void* src[3] = {s->S(s->cur), s->phi(), s->status()};
+  void* dst[3] = {b, b + sb, b + sb + pb};
+  const size_t bytes[3] = {sb, pb, sizeof(int)};
   // the rest of the blob is zero, so equal states give equal blobs
-  constexpr int kTailInts = (int)((kAlign - sizeof(int)) / sizeof(int));
-  HIPCHK(launch_fill_int((int*)(b + sb + pb + sizeof(int)), 0, kTailInts, st));
+  HIPCHK(launch_copies(src, dst, bytes, 3, b + sb + pb + sizeof(int), kAlign - sizeof(int), (hipStream_t)stream));
   return LBM_OK;
 }
 
 int lbm_restore(lbm_sim* s, const void* d_blob, void* stream) {
   if (!s || !d_blob) return fail(LBM_E_INVAL, "NULL argument");
-  hipStream_t st = (hipStream_t)stream;
   const size_t sb = s->state_floats() * sizeof(float), pb = (size_t)s->L.g.ps * sizeof(double);
   const char* b = (const char*)d_blob;
-  HIPCHK(hipMemcpyAsync(s->S(s->cur), b, sb, hipMemcpyDeviceToDevice, st));
-  HIPCHK(hipMemcpyAsync(s->phi(), b + sb, pb, hipMemcpyDeviceToDevice, st));
-  HIPCHK(hipMemcpyAsync(s->status(), b + sb + pb, sizeof(int), hipMemcpyDeviceToDevice, st));
+  const void* src[3] = {b, b + sb, b + sb + pb};
+  void* dst[3] = {s->S(s->cur), s->phi(), s->status()};
+  const size_t bytes[3] = {sb, pb, sizeof(int)};
+  HIPCHK(launch_copies(src, dst, bytes, 3, nullptr, 0, (hipStream_t)stream));
   return LBM_OK;
 }
 

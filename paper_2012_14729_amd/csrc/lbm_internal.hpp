@@ -127,6 +127,10 @@ hipError_t launch_init(const float* phi0, const float* ux0, const float* uy0, fl
 hipError_t launch_phi_sum(const double* phi, const Grid& g, double* partial, int npartial, double* out,
                           hipStream_t s);
 hipError_t launch_fill_int(int* p, int value, int n, hipStream_t s);
+// njobs (<= 3) copies of bytes[k] from src[k] to dst[k], then zero_bytes of
+// zeros at `zero` (nullable), as one launch; sizes multiples of 4 bytes.
+hipError_t launch_copies(const void* const* src, void* const* dst, const size_t* bytes, int njobs, void* zero,
+                         size_t zero_bytes, hipStream_t s);
 // persistent batched step kernels over a tile list (periodic instances); form < 0:
 // one kernel for every form, else the tiles [t0, t1) all have that form
 hipError_t launch_batch_fused(const BatchInst* inst, const TileRef* tiles, int t0, int t1, int form, int fast,

@@ -925,6 +925,30 @@ __global__ __launch_bounds__(256) void k_sum_final(const double* __restrict__ pa
   if (threadIdx.x == 0) *out = red[0];
 }
 
+// Up to three device copies and one zero fill in one launch (checkpoints):
+// every byte count is a multiple of 4 and every pointer 4-byte aligned.
+struct CopyJob {
+  const unsigned* src[3];
+  unsigned* dst[3];
+  long long n[3];        // words
+  unsigned* zero;        // words set to 0
+  long long nzero;
+};
+
+__global__ __launch_bounds__(256) void k_copy_jobs(CopyJob j) {
+  const long long tot = j.n[0] + j.n[1] + j.n[2] + j.nzero;
+  for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < tot; k += (long long)gridDim.x * 256) {
+    long long r = k;
+    if (r < j.n[0]) { j.dst[0][r] = j.src[0][r]; continue; }
+    r -= j.n[0];
+    if (r < j.n[1]) { j.dst[1][r] = j.src[1][r]; continue; }
+    r -= j.n[1];
+    if (r < j.n[2]) { j.dst[2][r] = j.src[2][r]; continue; }
+    r -= j.n[2];
+    j.zero[r] = 0u;
+  }
+}
+
 __global__ void k_fill_int(int* p, int v, int n) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) p[k] = v;
@@ -998,6 +1022,25 @@ hipError_t launch_phi_sum(const double* phi, const Grid& g, double* partial, int
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, partial, npartial, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_copies(const void* const* src, void* const* dst, const size_t* bytes, int njobs, void* zero,
+                         size_t zero_bytes, hipStream_t s) {
+  CopyJob j{};
+  long long tot = 0;
+  for (int k = 0; k < 3; ++k) {
+    j.src[k] = k < njobs ? (const unsigned*)src[k] : nullptr;
+    j.dst[k] = k < njobs ? (unsigned*)dst[k] : nullptr;
+    j.n[k] = k < njobs ? (long long)(bytes[k] / 4) : 0;
+    tot += j.n[k];
+  }
+  j.zero = (unsigned*)zero;
+  j.nzero = zero ? (long long)(zero_bytes / 4) : 0;
+  tot += j.nzero;
+  const long long want = (tot + 255) / 256;
+  const unsigned blocks = (unsigned)(want < 8192 ? (want < 1 ? 1 : want) : 8192);
+  hipLaunchKernelGGL(k_copy_jobs, dim3(blocks), dim3(256), 0, s, j);
   return hipGetLastError();
 }
 

@@ -184,3 +184,25 @@ def test_gradients_match_fp64_central_differences_shear_64x32():
     assert abs(L - L0) <= 1e-4 * L0
     assert e_s < 1e-5 and e_m < 1e-5
     assert e_p < 5e-5
+
+
+def test_step_blob_equals_restore_then_step():
+    """lbm_adjoint_step_blob about a saved state gives the same lambda, bit for
+    bit, as restoring that state and calling lbm_adjoint_step."""
+    import paper_2012_14729_amd as P
+    p, phi0, ux0, uy0 = WL.config_shear(nx=80, ny=40, R=8.0, Re=1.0, Ca=0.2)
+    sim = P.Simulation(p.as_dict(), np.asarray(phi0, np.float32), ux0, uy0)
+    sim.step(5, "csf1")
+    blob = sim.save()
+    sim.step(3, "csf1")          # move the simulation away from the saved state
+    adj = P.Adjoint(sim)
+    g = torch.Generator().manual_seed(3)
+    lam0 = torch.randn((20, p.ny, p.nx), generator=g, dtype=torch.float64).to("cuda")
+    a = adj.step_blob(blob, lam0.clone(), "csf1")
+    ga = adj.param_grads()
+    adj.reset()
+    sim.restore(blob)
+    b = adj.step(lam0.clone(), "csf1")
+    gb = adj.param_grads()
+    assert torch.equal(a, b)
+    assert ga == gb
