@@ -4,10 +4,11 @@
 
 Workload: the stationary droplet on a 2048x2048 periodic lattice (R = 256,
 W = 5, density ratio 1000, dynamic viscosity ratio 100, sigma = 1e-3), one
-simulation per interfacial-force form; a "step" is one time step (fused
+run per interfacial-force form; a "step" is one time step (fused
 collide-stream kernel + order-parameter kernel) of one of the eight
-simulations, taken round-robin, so K steps cover every form.  All state is
-resident in HBM before the timed region.
+simulations.  The timed K steps are eight consecutive runs of K/8 steps, one
+per form, back to back.  All state is resident in HBM before the timed
+region.
 
 Prints one JSON line with MLUPS, the roofline of the fused kernel (HIP
 events recorded on the launch stream during the timed region), the oracle
@@ -213,17 +214,22 @@ def main():
     sims = [P.Simulation(p.as_dict(), phi0, device=dev) for _ in FORMS]
     cells = p.nx * p.ny
 
-    for k in range(args.warmup):
-        sims[k % 8].step(1, FORMS[k % 8])
+    if args.steps % 8:
+        print("bench.py: --steps must be a multiple of 8 (one run per force form)", file=sys.stderr)
+        sys.exit(2)
+    for k, (s, f) in enumerate(zip(sims, FORMS)):
+        s.step(max(1, args.warmup // 8), f)
     torch.cuda.synchronize()
     print("[bench] warm-up done", file=sys.stderr, flush=True)
 
     for s in sims:
         s.set_timing(True)
     torch.cuda.synchronize()
+    per = args.steps // 8
     t0 = time.perf_counter()
-    for k in range(args.steps):
-        sims[k % 8].step(1, FORMS[k % 8])
+    for s, f in zip(sims, FORMS):
+        for _ in range(per):
+            s.step(1, f)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     fused_ms = sum(s.kernel_time(0)[0] for s in sims)
@@ -267,7 +273,7 @@ def main():
         "ms_per_step": round(el / args.steps * 1e3, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"stationary droplet {p.nx}x{p.ny} periodic, R={p.nx // 8}, W=5, rho1/rho2=1000, "
-                               f"mu1/mu2=100, sigma=1e-3, 8 force forms round-robin",
+                               f"mu1/mu2=100, sigma=1e-3, one run per force form (8 runs of steps/8)",
                    "precision": "FP32 storage of f, h, J, P; FP64 arithmetic (collision, stencils, forces) and FP64 phi",
                    "step_bytes_per_node": BYTES_FUSED + BYTES_PHI,
                    "step_GBs": round((BYTES_FUSED + BYTES_PHI) * value * 1e6 / 1e9, 1)},
