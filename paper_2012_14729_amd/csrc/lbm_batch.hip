@@ -4,9 +4,10 @@
 //   [instance descriptors][tile list][status ints][rho0 sums][partial sums]
 //   then, per instance, the same arrays as a single lattice (two interleaved
 //   state arrays, FP64 phi).
-// A step is persistent launches over one tile list covering every instance
-// (sorted by force form): the fused collide-stream kernel (one launch for
-// every form, or one per form) and the order-parameter kernel.  Steps are
+// A step is launches over one tile list covering every instance (sorted by
+// force form): the fused collide-stream kernel (one launch for every form, or
+// one per form; persistent workgroups or one per tile) and the order-parameter
+// kernel (one workgroup per tile).  Steps are
 // replayed from a HIP graph captured once per batch (buffer A -> B -> A ...),
 // so the host issues one graph launch per kChunk steps.
 //
@@ -155,7 +156,10 @@ int launch_pair_steps(lbm_batch* b, const BatchCfg& c, int nsteps, int parity0, 
       BHIP(launch_batch_fused(b->d_inst(), b->d_tiles(), 0, b->L.ntiles, -1, c.fast, par, grid_for(b, c, b->L.ntiles),
                               st));
     }
-    BHIP(launch_batch_phi(b->d_inst(), b->d_tiles(), b->L.ntiles, par, grid_for(b, c, b->L.ntiles), st));
+    // The order-parameter pass holds few registers: one workgroup per tile
+    // keeps far more of them resident than the fused kernel's persistent grid.
+    BHIP(launch_batch_phi(b->d_inst(), b->d_tiles(), b->L.ntiles, par, grid_for(b, BatchCfg{c.split, c.fast, 0, 0.0},
+                                                                                 b->L.ntiles), st));
     par = 1 - par;
   }
   return LBM_OK;
