@@ -25,7 +25,7 @@ f_i(x, n), h_i(x, n) plus J = (phi u) of the previous step.  One call to
 to time n+1 (with bounce-back at walls).
 
 The readings taken where the paper is silent or garbled are listed next to
-the code that uses them (labels A1..A22 as in the design notes):
+the code that uses them (labels A1..A23 as in the design notes):
   A1  forcing term of Eq. (35): Gamma_i = w_i (1 + s_i) and the pressure
       gradient term is w_i s_i grad(cs^2 rho);
   A3  the factor 3 in Eq. (36) is 1/cs^2;
@@ -45,7 +45,9 @@ the code that uses them (labels A1..A22 as in the design notes):
       h = h^eq(phi0, mu(phi0), u0);
   A12 rho0 (background density of F_g): if not given, the mean of rho(phi0)
       over the domain, fixed for the run;
-  A18 second-level derivatives apply the same stencil twice.
+  A18 second-level derivatives apply the same stencil twice;
+  A23 the hydrodynamic pressure of STF-1 is P_sf + kappa |grad(phi)|^2 (the
+      sign printed after Eq. 17 contradicts Eqs. 19, 21 and 26).
 """
 from __future__ import annotations
 
@@ -433,6 +435,52 @@ def step(state, form: str, p: Params):
     fnew = _stream(fpost, lambda i, cu: 2.0 * WT[i] * rho * cu, p)
     hnew = _stream(hpost, lambda i, cu: 2.0 * WT[i] * phi * cu / CS2, p)
     return dict(f=fnew, h=hnew, J=torch.stack([qx, qy]), rho0=state["rho0"], t=state["t"] + 1)
+
+
+# ----------------------------------------------------------------------------
+# Hydrodynamic pressure (Sec. II.B).  Each force form moves different gradient
+# terms into the generalised pressure P_sf of the momentum equation, so
+# p_h = P_sf - D_form:
+#   STF-1  D = -kappa |grad phi|^2        (reading A23: from Eq. 19, see below)
+#   STF-2  D = 0                          (text after Eq. 18)
+#   CPF-1  D = f0 - phi mu_phi - (kappa/2) |grad phi|^2      (Eq. 21)
+#   CPF-2  D = f0 - (kappa/2) |grad phi|^2                   (Eq. 21)
+#   PF-1   D = -(kappa/2) |grad phi|^2                       (Eq. 21)
+#   PF-2   D = kappa phi lap(phi) - (kappa/2) |grad phi|^2   (Eq. 21)
+#   CSF-1, CSF-2  D = 0 (the CSF force holds no gradient term; Sec. II.B after
+#                  Eq. 26, the pressure of the CSF model is p_h)
+# with f0 = beta (1 - phi^2)^2.  A23: the text after Eq. (17) prints
+# P_stf-1 = p_h + kappa |grad phi|^2, but Eq. (19) gives
+# F_stf-1 = F_pf-1 - grad(kappa |grad phi|^2 / 2), so with Eq. (21)'s
+# P_pf-1 = p_h - (kappa/2)|grad phi|^2 the consistent value is
+# P_stf-1 = p_h - kappa |grad phi|^2 (the same follows from Eq. 26 against
+# STF-2).  Derivatives are the isotropic stencils of Eqs. (41)-(42).
+# ----------------------------------------------------------------------------
+def pressure_offset(m, form: str, c: Const):
+    """D_form of a macroscopic() result m (fields phi, mu, gx, gy, lap)."""
+    phi = m["phi"]
+    g2 = m["gx"] * m["gx"] + m["gy"] * m["gy"]
+    f0 = c.beta * (1.0 - phi * phi) ** 2
+    if form == "stf1":
+        return -c.kappa * g2
+    if form in ("stf2", "csf1", "csf2"):
+        return torch.zeros_like(phi)
+    if form == "cpf1":
+        return f0 - phi * m["mu"] - 0.5 * c.kappa * g2
+    if form == "cpf2":
+        return f0 - 0.5 * c.kappa * g2
+    if form == "pf1":
+        return -0.5 * c.kappa * g2
+    if form == "pf2":
+        return c.kappa * phi * m["lap"] - 0.5 * c.kappa * g2
+    raise ValueError(f"unknown force form {form!r}")
+
+
+def hydro_pressure(state, form: str, p: Params):
+    """p_h = P_sf - D_form of a state (what lbm_hydro_pressure returns)."""
+    c = constants(p)
+    m = macroscopic(state["f"], state["h"], state["J"], state["rho0"], form, p, c)
+    return m["P"] - pressure_offset(m, form, c)
 
 
 def run(state, form: str, p: Params, nsteps: int):
