@@ -114,6 +114,16 @@ int lbm_step(lbm_sim* sim, int32_t nsteps, int32_t force_form, void* stream);
 int lbm_moments(lbm_sim* sim, int32_t force_form, float* d_phi, float* d_rho, float* d_ux, float* d_uy,
                 float* d_p, void* stream);
 
+/* Hydrodynamic pressure of the current state (Sec. II.B): p_h = P_sf - D,
+ * where D holds the gradient terms the force form moves into its
+ * generalised pressure P_sf (Eq. 21 for CPF-1/2 and PF-1/2, with
+ * f0 = beta (1 - phi^2)^2; D = 0 for STF-2, CSF-1, CSF-2; D = -kappa |grad phi|^2
+ * for STF-1, the value Eqs. 19 and 26 give).  Stencils as in the step
+ * (Eqs. 41-42).  d_ph: caller-owned device buffer of nx*ny floats, row-major
+ * [y][x]; must not be NULL.  Asynchronous on `stream`.  LBM_E_INVAL for a
+ * NULL argument or a bad form. */
+int lbm_hydro_pressure(lbm_sim* sim, int32_t force_form, float* d_ph, void* stream);
+
 /* Host-side query: synchronises `stream`; *diverged = 1 if any step since
  * init produced a non-finite velocity or order parameter, else 0.  Returns
  * LBM_E_DIVERGED in that case (with *diverged = 1). */

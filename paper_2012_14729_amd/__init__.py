@@ -99,6 +99,17 @@ class Simulation:
                                 _ptr(out.get("ux")), _ptr(out.get("uy")), _ptr(out.get("P")), _stream(stream)))
         return out
 
+    def hydro_pressure(self, form, stream=None, out=None):
+        """p_h = P_sf - D_form of the current state (lbm_hydro_pressure)."""
+        out = out if out is not None else torch.empty((self.ny, self.nx), dtype=torch.float32,
+                                                      device=self.workspace.device)
+        if (out.dtype != torch.float32 or tuple(out.shape) != (self.ny, self.nx) or not out.is_contiguous()
+                or out.device != self.workspace.device):
+            raise ValueError(f"out must be a contiguous float32 [{self.ny}, {self.nx}] tensor on "
+                             f"{self.workspace.device}")
+        check(lib().lbm_hydro_pressure(self._h, form_index(form), _ptr(out), _stream(stream)))
+        return out
+
     def status(self, stream=None):
         d = C.c_int32()
         code = lib().lbm_status(self._h, C.byref(d), _stream(stream))

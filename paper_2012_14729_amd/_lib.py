@@ -45,6 +45,7 @@ _SIGS = {
     "lbm_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
     "lbm_moments": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                               C.c_void_p]),
+    "lbm_hydro_pressure": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "lbm_status": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_void_p]),
     "lbm_get_step": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     "lbm_state_bytes": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),

@@ -323,7 +323,15 @@ int lbm_moments(lbm_sim* s, int32_t form, float* d_phi, float* d_rho, float* d_u
                 void* stream) {
   if (!s) return fail(LBM_E_INVAL, "sim is NULL");
   if (form < 0 || form >= LBM_NUM_FORMS) return fail(LBM_E_INVAL, "bad force form %d", form);
-  MomentArgs m{d_phi, d_rho, d_ux, d_uy, d_p};
+  MomentArgs m{d_phi, d_rho, d_ux, d_uy, d_p, nullptr};
+  HIPCHK(launch_moments(form, step_args(s), m, (hipStream_t)stream));
+  return LBM_OK;
+}
+
+int lbm_hydro_pressure(lbm_sim* s, int32_t form, float* d_ph, void* stream) {
+  if (!s || !d_ph) return fail(LBM_E_INVAL, "NULL argument");
+  if (form < 0 || form >= LBM_NUM_FORMS) return fail(LBM_E_INVAL, "bad force form %d", form);
+  MomentArgs m{nullptr, nullptr, nullptr, nullptr, nullptr, d_ph};
   HIPCHK(launch_moments(form, step_args(s), m, (hipStream_t)stream));
   return LBM_OK;
 }

@@ -433,7 +433,7 @@ int lbm_batch_step(lbm_batch* b, int32_t nsteps, void* stream) {
 int lbm_batch_moments(lbm_batch* b, int32_t k, float* d_phi, float* d_rho, float* d_ux, float* d_uy, float* d_p,
                       void* stream) {
   if (!b || k < 0 || k >= b->count) return bfail(LBM_E_INVAL, "bad batch or instance index");
-  MomentArgs m{d_phi, d_rho, d_ux, d_uy, d_p};
+  MomentArgs m{d_phi, d_rho, d_ux, d_uy, d_p, nullptr};
   BHIP(launch_moments(b->forms[k], b->host[k].a[b->parity], m, (hipStream_t)stream));
   return LBM_OK;
 }

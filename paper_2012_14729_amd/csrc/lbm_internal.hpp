@@ -81,6 +81,7 @@ struct MomentArgs {
   float* ux;
   float* uy;
   float* p;
+  float* ph;   // hydrodynamic pressure p_h = P_sf - D_form (Sec. II.B)
 };
 
 // One instance of a batch: its step arguments for both ping-pong parities

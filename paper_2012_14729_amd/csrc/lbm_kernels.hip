@@ -346,6 +346,26 @@ __device__ __forceinline__ void velocity_from(const Lds& s, const StepArgs& a, i
   }
 }
 
+// D_form = P_sf - p_h at velocity-ring position (uy_, ux_): the gradient
+// terms each force form moves into its generalised pressure (Sec. II.B,
+// Eq. 21 for CPF and PF; zero for STF-2 and CSF).  STF-1 takes
+// -kappa |grad phi|^2, the value Eqs. (19) and (26) give (the sign printed
+// with Eq. 17 contradicts them).  f0 = beta (1 - phi^2)^2.
+template <int FORM>
+__device__ __forceinline__ double pressure_offset(const Lds& s, int uy_, int ux_, const Phys& c) {
+  const double phi = s.phi[uy_ + 2][ux_ + 2];
+  const double gx = s.gl[0][uy_ + 1][ux_ + 1], gy = s.gl[1][uy_ + 1][ux_ + 1], lap = s.gl[2][uy_ + 1][ux_ + 1];
+  const double kg2 = c.kappa_d * (gx * gx + gy * gy);
+  const double om = (1.0 - phi) * (1.0 + phi);
+  const double f0 = 0.25 * c.beta4_d * om * om;
+  if constexpr (FORM == 0) return -kg2;
+  else if constexpr (FORM == 2) return f0 - phi * chem_pot(phi, lap, c) - 0.5 * kg2;
+  else if constexpr (FORM == 3) return f0 - 0.5 * kg2;
+  else if constexpr (FORM == 4) return -0.5 * kg2;
+  else if constexpr (FORM == 5) return c.kappa_d * phi * lap - 0.5 * kg2;
+  else return 0.0;   // STF-2, CSF-1, CSF-2
+}
+
 __device__ __forceinline__ bool in_domain(int x, int y, const Grid& g) { return x >= 0 && x < g.nx && y >= 0 && y < g.ny; }
 
 // Velocity-ring position k -> (uy_, ux_)
@@ -563,6 +583,7 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
       if (m.ux) m.ux[om] = (float)n.ux;
       if (m.uy) m.uy[om] = (float)n.uy;
       if (m.p) m.p[om] = (float)n.P;
+      if (m.ph) m.ph[om] = (float)(n.P - pressure_offset<FORM>(s, uy_, ux_, c));
     }
     return;
   } else {

@@ -1,0 +1,77 @@
+"""The physical/dimensionless -> lattice front-end (paper_2012_14729_amd.units)
+against the definitions of Sec. II.A and the benchmark recipes of Sec. V.
+
+Pins: the groups recomputed straight from their definitions on the returned
+lattice parameters; the rising-bubble numbers computed independently by the
+channel workload; the small-deformation closed form at the values the
+paper prints in Table VI's last row."""
+import json
+import math
+import os
+
+import pytest
+
+from paper_2012_14729_amd import units as U
+import workloads as WL
+
+
+def test_lattice_params_realise_the_groups():
+    g = U.Groups(Re=35.0, We=12.0, Pe=250.0, Cn=0.05, Fr=0.8, rho_ratio=1e-3, mu_ratio=1e-2)
+    L, Uc = 80.0, 0.02
+    p = U.lattice_params(g, L, Uc, rho1=1.0)
+    # the definitions of Sec. II.A, evaluated directly
+    beta = 3 * p["sigma"] / (4 * p["W"])
+    assert math.isclose(1.0 * Uc * L / (p["rho1"] * p["nu1"]), g.Re, rel_tol=1e-12)
+    assert math.isclose(p["rho1"] * L * Uc ** 2 / p["sigma"], g.We, rel_tol=1e-12)
+    assert math.isclose(Uc * L / (4 * p["M"] * beta), g.Pe, rel_tol=1e-12)
+    assert math.isclose(p["W"] / L, g.Cn, rel_tol=1e-12)
+    assert math.isclose(Uc / math.sqrt(-p["gy"] * L), g.Fr, rel_tol=1e-12)
+    assert p["gx"] == 0.0
+    assert math.isclose(p["rho2"] / p["rho1"], 1e-3) and math.isclose(p["rho2"] * p["nu2"] / p["nu1"], 1e-2)
+    back = U.groups_of(p, L, Uc)
+    for k in ("Re", "We", "Pe", "Cn", "Fr", "rho_ratio", "mu_ratio"):
+        assert math.isclose(getattr(back, k), getattr(g, k), rel_tol=1e-12), k
+
+
+def test_no_gravity_and_passthrough():
+    p = U.lattice_params(U.Groups(Re=10, We=1, Pe=100, Cn=0.1), 40, 0.01, nx=128, ny=64, wall_y=1)
+    assert p["gx"] == 0.0 and p["gy"] == 0.0 and p["nx"] == 128 and p["wall_y"] == 1
+    assert U.groups_of(p, 40, 0.01).Fr is None
+
+
+def test_rejects_supersonic_reference_velocity():
+    with pytest.raises(ValueError):
+        U.lattice_params(U.Groups(Re=10, We=1, Pe=100, Cn=0.1), 40, 0.6)
+
+
+def test_rising_bubble_recipe_matches_channel_workload():
+    """Eo = 10, Mo = 1e-3, U_g = 0.01, R = 128 (the 1024x4096 channel)."""
+    p = U.rising_bubble_params(R=128.0, Eo=10.0, Mo=1e-3, U_g=0.01)
+    w = WL.config_bubble()[0].as_dict()
+    for k in ("rho1", "rho2", "nu1", "nu2", "sigma", "gy"):
+        assert math.isclose(p[k], w[k], rel_tol=1e-12), k
+    # the groups of Sec. V.D back from the lattice values
+    L, Ug = 256.0, math.sqrt(2 * 128.0 * -p["gy"])
+    Re = p["rho1"] * Ug * L / (p["rho1"] * p["nu1"])
+    Eo = p["rho1"] * Ug ** 2 * L / p["sigma"]
+    assert math.isclose(Ug, 0.01, rel_tol=1e-12)
+    assert math.isclose(Eo, 10.0, rel_tol=1e-12)
+    assert math.isclose(Eo ** 3 / Re ** 4, 1e-3, rel_tol=1e-12)
+    assert math.isclose(U.tau_f(p["nu1"]), 0.5 + 3 * p["nu1"])
+
+
+def test_shear_recipe_matches_shear_workload():
+    p = U.shear_drop_params(R=64.0, H=256.0, Re=1.0, Ca=0.2)
+    w = WL.config_shear()[0].as_dict()
+    for k in ("u_wall_lo", "u_wall_hi", "sigma", "nu1", "nu2"):
+        assert math.isclose(p[k], w[k], rel_tol=1e-12), k
+    E = (p["u_wall_hi"] - p["u_wall_lo"]) / 256.0
+    assert math.isclose(E * 64.0 ** 2 / p["nu1"], 1.0, rel_tol=1e-12)
+    assert math.isclose(p["nu1"] * E * 64.0 / p["sigma"], 0.2, rel_tol=1e-12)
+
+
+def test_taylor_deformation_matches_printed_theory_row():
+    """Table VI, row 'Eq. (52)': viscosity ratio 1 at Ca = 0.1..0.4."""
+    tab = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table6_taylor.json")))
+    for ca, d in zip(tab["Ca"], tab["theory_rho1"]):
+        assert abs(U.taylor_deformation(ca, 1.0) - d) < 6e-5, (ca, d)
