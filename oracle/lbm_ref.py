@@ -13,6 +13,7 @@ Follows Zhang, Liang & Guo, arXiv:2012.14729:
                 Eq. 40), isotropic difference stencils (Eqs. 41-42);
   Sec. IV    -- half-way bounce-back with moving walls (Eq. 43) and the
                 order-parameter wall condition (Eq. 44);
+  Sec. V.D   -- free-slip side walls of the rising-bubble test (reading A24);
   Sec. V     -- explicit-Euler time derivative and the modified weights
                 (opening paragraph of Sec. V).
 
@@ -47,7 +48,11 @@ the code that uses them (labels A1..A23 as in the design notes):
       over the domain, fixed for the run;
   A18 second-level derivatives apply the same stencil twice;
   A23 the hydrodynamic pressure of STF-1 is P_sf + kappa |grad(phi)|^2 (the
-      sign printed after Eq. 17 contradicts Eqs. 19, 21 and 26).
+      sign printed after Eq. 17 contradicts Eqs. 19, 21 and 26);
+  A24 a free-slip wall (named, not specified, in Sec. V.D) is a half-way
+      plane of mirror symmetry: links crossing it reflect specularly, phi is
+      extended evenly, the ghost velocity mirrors (normal component negated,
+      tangential copied); a link into a corner bounces back.
 """
 from __future__ import annotations
 
@@ -77,8 +82,8 @@ class Params:
     """Problem statement in lattice units (mirrors the C struct lbm_params)."""
     nx: int
     ny: int
-    wall_x: int = 0          # 1: half-way walls at x = -1/2 and x = nx - 1/2
-    wall_y: int = 0          # 1: half-way walls at y = -1/2 and y = ny - 1/2
+    wall_x: int = 0          # half-way walls at x = -1/2 and x = nx - 1/2: 1 no-slip, 2 free-slip
+    wall_y: int = 0          # half-way walls at y = -1/2 and y = ny - 1/2: 1 no-slip, 2 free-slip
     u_wall_lo: float = 0.0   # tangential speed of the low wall of the walled axis
     u_wall_hi: float = 0.0   # tangential speed of the high wall
     rho1: float = 1.0        # fluid 1 (phi = +1)
@@ -155,13 +160,18 @@ def _wall_velocity(p: Params):
 
 
 def extend_velocity(ux: torch.Tensor, uy: torch.Tensor, p: Params):
-    """Extend u by one ghost layer: periodic wrap, or u_ghost = 2 u_w - u_mirror
-    at a half-way wall (reading A9)."""
+    """Extend u by one ghost layer: periodic wrap; u_ghost = 2 u_w - u_mirror
+    at a no-slip half-way wall (reading A9); at a free-slip wall (a plane of
+    mirror symmetry) the normal component changes sign and the tangential
+    one is copied.  x is extended first, then y (corners compose both)."""
     (lox, loy), (hix, hiy) = _wall_velocity(p)
 
-    def ext(a, dim, wall, lo_w, hi_w):
+    def ext(a, dim, wall, lo_w, hi_w, sign):
         n = a.shape[dim]
-        if wall:
+        if wall == 2:
+            lo = sign * a.narrow(dim, 0, 1)
+            hi = sign * a.narrow(dim, n - 1, 1)
+        elif wall:
             lo = 2.0 * lo_w - a.narrow(dim, 0, 1)
             hi = 2.0 * hi_w - a.narrow(dim, n - 1, 1)
         else:
@@ -169,10 +179,10 @@ def extend_velocity(ux: torch.Tensor, uy: torch.Tensor, p: Params):
             hi = a.narrow(dim, 0, 1)
         return torch.cat([lo, a, hi], dim=dim)
 
-    ux = ext(ux, 1, bool(p.wall_x), lox, hix)
-    uy = ext(uy, 1, bool(p.wall_x), loy, hiy)
-    ux = ext(ux, 0, bool(p.wall_y), lox, hix)
-    uy = ext(uy, 0, bool(p.wall_y), loy, hiy)
+    ux = ext(ux, 1, p.wall_x, lox, hix, -1.0)
+    uy = ext(uy, 1, p.wall_x, loy, hiy, 1.0)
+    ux = ext(ux, 0, p.wall_y, lox, hix, 1.0)
+    uy = ext(uy, 0, p.wall_y, loy, hiy, -1.0)
     return ux, uy
 
 
@@ -344,10 +354,22 @@ def moments(state, form: str, p: Params):
 # ----------------------------------------------------------------------------
 # Streaming with half-way bounce-back (Eqs. 29-30 left-hand sides; Eq. 43)
 # ----------------------------------------------------------------------------
+def _mirror(i: int, axis: str) -> int:
+    """Direction with the x (or y) component of c_i reversed."""
+    cx, cy = (-CX[i], CY[i]) if axis == "x" else (CX[i], -CY[i])
+    return next(j for j in range(9) if CX[j] == cx and CY[j] == cy)
+
+
 def _stream(post, wall_value, p: Params):
     """post: [9, ny, nx] post-collision populations.  wall_value(i, u_w, src_mask)
     returns the moving-wall correction subtracted when direction i leaves the
-    domain.  Returns the populations at the next time step."""
+    domain.  Returns the populations at the next time step.
+
+    A link that crosses a no-slip wall bounces back to its own node (Eq. 43).
+    A link that crosses only a free-slip wall is reflected specularly: the
+    normal component of c_i reverses and the population lands on the node
+    beside its origin, shifted along the wall by the tangential component.
+    A link into a corner (both axes at once) bounces back."""
     ny, nx = p.ny, p.nx
     new = torch.zeros_like(post)
     ys = torch.arange(ny).view(ny, 1).expand(ny, nx)
@@ -360,7 +382,13 @@ def _stream(post, wall_value, p: Params):
         dx, dy = dx % nx, dy % ny
         inside = ~(out_x | out_y)
         new[i][dy[inside], dx[inside]] = post[i][inside]
-        out = ~inside
+        slip_x = out_x & ~out_y if p.wall_x == 2 else torch.zeros_like(out_x)
+        slip_y = out_y & ~out_x if p.wall_y == 2 else torch.zeros_like(out_y)
+        if bool(slip_x.any()):           # lands on (x, y + c_iy)
+            new[_mirror(i, "x")][dy[slip_x], xs[slip_x]] = post[i][slip_x]
+        if bool(slip_y.any()):           # lands on (x + c_ix, y)
+            new[_mirror(i, "y")][ys[slip_y], dx[slip_y]] = post[i][slip_y]
+        out = ~(inside | slip_x | slip_y)
         if bool(out.any()):
             # wall velocity of the wall the link crosses (low or high side)
             uwx = torch.zeros((ny, nx), dtype=torch.float64)
@@ -395,7 +423,8 @@ def init(p: Params, phi0: torch.Tensor, ux0=None, uy0=None):
     """Initial state from phi0 (and optional u0): P0 = 0,
     f_i = f_i^eq(0, rho(phi0), u0), h_i = h_i^eq(phi0, mu(phi0), u0), J = phi0 u0."""
     c = constants(p)
-    phi0 = phi0
+    if (p.wall_x == 2 or p.wall_y == 2) and (p.u_wall_lo != 0.0 or p.u_wall_hi != 0.0):
+        raise ValueError("free-slip walls do not move, and moving walls need exactly one walled axis")
     zeros = torch.zeros_like(phi0)
     ux0 = zeros if ux0 is None else ux0.to(phi0.dtype)
     uy0 = zeros if uy0 is None else uy0.to(phi0.dtype)
