@@ -62,13 +62,17 @@ enum lbm_status_code {
 };
 
 /* Problem statement in lattice units (Sec. II.A, Sec. III, Sec. IV).
- * Validation (LBM_E_INVAL): nx, ny >= 8; wall_x, wall_y in {0, 1}; at most
- * one walled axis may have moving walls; rho1, rho2 > 0; nu1, nu2 > 0 (so
+ * Validation (LBM_E_INVAL): nx, ny >= 8; wall_x, wall_y in {0, 1, 2}; at
+ * most one walled axis may have moving walls, and free-slip walls do not
+ * move; rho1, rho2 > 0; nu1, nu2 > 0 (so
  * tau_f = 1/2 + 3 nu > 1/2 everywhere); sigma >= 0; W > 0; M >= 0;
  * tau_h > 1/2; eps_n > 0; all finite except rho0, which may be NaN. */
 typedef struct lbm_params {
   int32_t nx, ny;          /* nodes along x and y                                          */
-  int32_t wall_x, wall_y;  /* 0: periodic axis; 1: half-way bounce-back walls on that axis   */
+  int32_t wall_x, wall_y;  /* 0: periodic axis; 1: half-way no-slip (bounce-back) walls;     */
+                           /* 2: half-way free-slip walls (specular reflection, Sec. V.D's  */
+                           /*    side walls): a plane of mirror symmetry; links into a      */
+                           /*    corner bounce back                                          */
   double u_wall_lo;        /* tangential speed of the low wall of the walled axis (Eq. 43):  */
   double u_wall_hi;        /*   a y-wall moves along +x, an x-wall along +y                   */
   double rho1, rho2;       /* densities of fluid 1 (phi = +1) and fluid 2 (phi = -1) (Eq. 9) */
@@ -198,7 +202,8 @@ int lbm_batch_destroy(lbm_batch* batch);
 typedef struct lbm_adj lbm_adj;
 int lbm_adjoint_workspace_bytes(const lbm_params* p, size_t* bytes);
 /* Requires p->sigma > 0 (dL/dsigma is formed as dL/dF * F / sigma). Zeroes
- * the parameter-gradient accumulators (asynchronously on the null stream). */
+ * the parameter-gradient accumulators (asynchronously on the null stream).
+ * Free-slip walls (wall_x or wall_y = 2) return LBM_E_UNSUPPORTED. */
 int lbm_adjoint_create(lbm_adj** adj, lbm_sim* sim, void* d_ws, size_t ws_bytes);
 /* Zero the dL/dsigma, dL/dM accumulators. */
 int lbm_adjoint_reset(lbm_adj* adj, void* stream);

@@ -754,6 +754,10 @@ int lbm_adjoint_create(lbm_adj** out, lbm_sim* sim, void* d_ws, size_t ws_bytes)
   a->p = p;
   a->ws = (char*)d_ws;
   const int nx = p.nx, ny = p.ny;
+  if (p.wall_x == 2 || p.wall_y == 2) {
+    delete a;
+    return set_error(LBM_E_UNSUPPORTED, "the adjoint supports periodic and no-slip walls only");
+  }
   a->g.nx = nx; a->g.ny = ny; a->g.wx = p.wall_x; a->g.wy = p.wall_y;
   {
     SimView v;

@@ -53,10 +53,12 @@ int validate(const lbm_params* p) {
   if (p->nx < 8 || p->ny < 8) return fail(LBM_E_INVAL, "nx, ny must be >= 8 (got %d, %d)", p->nx, p->ny);
   if (21LL * (((long long)p->nx + 63) / 64 * 64) * p->ny >= (1LL << 32))
     return fail(LBM_E_INVAL, "grid too large (a 21-plane state array must hold fewer than 2^32 elements)");
-  if ((p->wall_x != 0 && p->wall_x != 1) || (p->wall_y != 0 && p->wall_y != 1))
-    return fail(LBM_E_INVAL, "wall_x, wall_y must be 0 or 1");
+  if (p->wall_x < 0 || p->wall_x > 2 || p->wall_y < 0 || p->wall_y > 2)
+    return fail(LBM_E_INVAL, "wall_x, wall_y must be 0 (periodic), 1 (no-slip) or 2 (free-slip)");
   if (p->wall_x && p->wall_y && (p->u_wall_lo != 0.0 || p->u_wall_hi != 0.0))
     return fail(LBM_E_INVAL, "moving walls need exactly one walled axis");
+  if ((p->wall_x == 2 || p->wall_y == 2) && (p->u_wall_lo != 0.0 || p->u_wall_hi != 0.0))
+    return fail(LBM_E_INVAL, "free-slip walls do not move");
   const double v[] = {p->u_wall_lo, p->u_wall_hi, p->rho1, p->rho2, p->nu1, p->nu2, p->sigma,
                       p->W,         p->M,         p->tau_h, p->gx,  p->gy,  p->eps_n};
   for (double d : v)
@@ -97,8 +99,8 @@ Phys pflbm::derive_phys(const lbm_params* p, double rho0) {
   c.rho0 = (float)rho0;
   c.uw_lo = (float)p->u_wall_lo;
   c.uw_hi = (float)p->u_wall_hi;
-  c.wall_x = p->wall_x;
-  c.wall_y = p->wall_y;
+  c.wall_x = p->wall_x != 0;   // walled axis (no-slip or free-slip; the kind is in Grid)
+  c.wall_y = p->wall_y != 0;
   c.beta4_d = 4.0 * beta;
   c.kappa_d = kappa;
   c.sigma_half_d = 0.5 * p->sigma;
@@ -140,6 +142,8 @@ Layout layout_for(const lbm_params* p) {
   L.g.fast = 1;
   if (const char* e = std::getenv("PFLBM_GENERAL_PATH"))   // diagnostics: every tile on the general path
     if (e[0] == '1') L.g.fast = 0;
+  L.g.slip_x = p->wall_x == 2;
+  L.g.slip_y = p->wall_y == 2;
   const size_t sbytes = (size_t)kNPL * (size_t)L.g.ps * sizeof(float);
   size_t o = 0;
   for (int b = 0; b < 2; ++b) { L.off_s[b] = o; o = align_up(o + sbytes, kAlign); }

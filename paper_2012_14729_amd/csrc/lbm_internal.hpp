@@ -25,6 +25,12 @@ __host__ __device__ constexpr int cy(int i) { return (i == 2 || i == 5 || i == 6
 __host__ __device__ constexpr float wt(int i) { return i == 0 ? 4.0f / 9.0f : (i < 5 ? 1.0f / 9.0f : 1.0f / 36.0f); }
 __host__ __device__ constexpr double wtd(int i) { return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0); }
 __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : (i < 5 ? ((i + 1) % 4) + 1 : ((i - 3) % 4) + 5); }
+// direction with the x (mirror_x) or y (mirror_y) component of c_i reversed
+__host__ __device__ constexpr int dir_of(int x, int y) {
+  return x == 0 ? (y == 0 ? 0 : (y > 0 ? 2 : 4)) : (x > 0 ? (y == 0 ? 1 : (y > 0 ? 5 : 8)) : (y == 0 ? 3 : (y > 0 ? 6 : 7)));
+}
+__host__ __device__ constexpr int mirror_x(int i) { return dir_of(-cx(i), cy(i)); }
+__host__ __device__ constexpr int mirror_y(int i) { return dir_of(cx(i), -cy(i)); }
 
 constexpr int kNPL = 21;  // planes of a state array
 constexpr int kPF = 0, kPH = 9, kPP = 18, kPJ = 19;   // first plane of f, h, P, J
@@ -58,6 +64,7 @@ struct Grid {
   long long ps;           // nodes of a padded plane (pitch * ny)
   int rowe;               // elements of one row of a state array (ncx * 21 * 64)
   int fast;               // interior tiles may take the fast addressing path
+  int slip_x, slip_y;     // the walls of that axis are free-slip (specular), not no-slip
 };
 
 // Element index of plane 0 of node (x, y) in a state array (21 ps < 2^32 is

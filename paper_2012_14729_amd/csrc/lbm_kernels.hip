@@ -53,22 +53,34 @@ __device__ __forceinline__ int halo_coord(int c, int n) {
 }
 
 // Source of the pulled population I for node (x, y) inside the domain: the
-// value that left x - c_I in direction I; if x - c_I lies beyond a wall the
-// slot opp(I) of x itself holds the bounced population (the wall term is
-// applied when it is stored).  Returns the element index of plane 0 of the
-// source node in a state array; `slot` is the direction to read there.
+// value that left x - c_I in direction I.  If x - c_I lies beyond a no-slip
+// wall, or beyond both walls of a corner, the slot opp(I) of x itself holds
+// the bounced population (the wall term is applied when it is stored).  A
+// link that crosses only a free-slip wall was reflected specularly: it left
+// the node beside x along the wall in the mirrored direction.  Returns the
+// element index of plane 0 of the source node in a state array; `slot` is
+// the direction to read there.
 template <int I>
 __device__ __forceinline__ unsigned src_base(int x, int y, const Grid& g, int wx, int wy, int& slot) {
   int sx = x - cx(I), sy = y - cy(I);
-  bool bounce = false;
+  bool out_x = false, out_y = false;
   if (cx(I) != 0) {
-    if (wx) bounce |= (sx < 0) | (sx >= g.nx);
+    if (wx) out_x = (sx < 0) | (sx >= g.nx);
     sx = sx < 0 ? sx + g.nx : (sx >= g.nx ? sx - g.nx : sx);
   }
   if (cy(I) != 0) {
-    if (wy) bounce |= (sy < 0) | (sy >= g.ny);
+    if (wy) out_y = (sy < 0) | (sy >= g.ny);
     sy = sy < 0 ? sy + g.ny : (sy >= g.ny ? sy - g.ny : sy);
   }
+  if (out_x && !out_y && g.slip_x) {
+    slot = mirror_x(I);
+    return nbase(g, x, sy);
+  }
+  if (out_y && !out_x && g.slip_y) {
+    slot = mirror_y(I);
+    return nbase(g, sx, y);
+  }
+  const bool bounce = out_x || out_y;
   slot = bounce ? opp(I) : I;
   return bounce ? nbase(g, x, y) : nbase(g, sx, sy);
 }
@@ -635,10 +647,10 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
         if (gy_) qy = uy_;
         vx = s.q[0][qy][qx];
         vy = s.q[1][qy][qx];
-        if (gx_ || gy_) {
+        if (gx_ || gy_) {   // a free-slip wall mirrors: only the normal component flips
           const float phm = (float)s.phi[qy + 2][qx + 2];
-          if (gx_) { vx = -vx; vy = 2.f * (nxg < 0 ? c.uw_lo : c.uw_hi) * phm - vy; }
-          if (gy_) { vx = 2.f * (nyg < 0 ? c.uw_lo : c.uw_hi) * phm - vx; vy = -vy; }
+          if (gx_) { vx = -vx; if (!g.slip_x) vy = 2.f * (nxg < 0 ? c.uw_lo : c.uw_hi) * phm - vy; }
+          if (gy_) { if (!g.slip_y) vx = 2.f * (nyg < 0 ? c.uw_lo : c.uw_hi) * phm - vx; vy = -vy; }
         }
       }
       dqf += wt(i) * dotcf(i, vx, vy);
@@ -904,12 +916,18 @@ __global__ __launch_bounds__(256) void k_init_unstream(const float* __restrict__
   const unsigned on = nbase(g, x, y);
 #pragma unroll
   for (int j = 0; j < 9; ++j) {
+    // the node that pulls this slot at the first step, and in which direction
+    // (the inverse of src_base: plain, specular at a free-slip wall, bounced)
     int tx = x + cx(j), ty = y + cy(j);
-    bool out = false;
-    if (wx) out |= (tx < 0) | (tx >= g.nx); else tx = (tx + g.nx) % g.nx;
-    if (wy) out |= (ty < 0) | (ty >= g.ny); else ty = (ty + g.ny) % g.ny;
-    const unsigned src = out ? on : nbase(g, tx, ty);
-    const int slot = out ? opp(j) : j;
+    bool out_x = false, out_y = false;
+    if (wx) out_x = (tx < 0) | (tx >= g.nx); else tx = (tx + g.nx) % g.nx;
+    if (wy) out_y = (ty < 0) | (ty >= g.ny); else ty = (ty + g.ny) % g.ny;
+    unsigned src;
+    int slot;
+    if (!out_x && !out_y) { src = nbase(g, tx, ty); slot = j; }
+    else if (out_x && !out_y && g.slip_x) { src = nbase(g, x, ty); slot = mirror_x(j); }
+    else if (out_y && !out_x && g.slip_y) { src = nbase(g, tx, y); slot = mirror_y(j); }
+    else { src = on; slot = opp(j); }
     s0[on + (unsigned)((kPF + j) * 64)] = s_tmp[src + (unsigned)((kPF + slot) * 64)];
     s0[on + (unsigned)((kPH + j) * 64)] = (j == 0) ? 0.0f : s_tmp[src + (unsigned)((kPH + slot) * 64)];
   }

@@ -56,13 +56,22 @@ def test_workspace_bytes_covers_state():
     assert n >= cells * (36 * 4 + 8 + 8)   # 2 x (f, h) + J + phi(FP64)
 
 
-@pytest.mark.parametrize("bad", [dict(nx=4), dict(ny=7), dict(wall_x=2), dict(tau_h=0.5), dict(nu1=0.0),
-                                 dict(rho2=-1.0), dict(W=0.0), dict(sigma=float("nan")), dict(eps_n=0.0),
-                                 dict(wall_x=1, wall_y=1, u_wall_hi=0.01), dict(rho0=float("inf"))])
+@pytest.mark.parametrize("bad", [dict(nx=4), dict(ny=7), dict(wall_x=3), dict(wall_y=-1), dict(tau_h=0.5),
+                                 dict(nu1=0.0), dict(rho2=-1.0), dict(W=0.0), dict(sigma=float("nan")),
+                                 dict(eps_n=0.0), dict(wall_x=1, wall_y=1, u_wall_hi=0.01),
+                                 dict(wall_y=2, u_wall_lo=-0.01), dict(wall_x=2, wall_y=1, u_wall_hi=0.01),
+                                 dict(rho0=float("inf"))])
 def test_invalid_params_rejected(bad):
     code, _ = ws_bytes(good(**bad))
     assert code == _lib.LBM_E_INVAL
     assert _lib.lib().lbm_last_error()
+
+
+@pytest.mark.parametrize("ok", [dict(wall_x=2), dict(wall_y=2), dict(wall_x=2, wall_y=2), dict(wall_x=2, wall_y=1),
+                                dict(wall_y=1, u_wall_lo=-0.01, u_wall_hi=0.01)])
+def test_wall_kinds_accepted(ok):
+    code, n = ws_bytes(good(**ok))
+    assert code == 0 and n > 0
 
 
 def test_init_rejects_null_and_misaligned_workspace():

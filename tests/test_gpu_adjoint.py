@@ -206,3 +206,14 @@ def test_step_blob_equals_restore_then_step():
     gb = adj.param_grads()
     assert torch.equal(a, b)
     assert ga == gb
+
+
+def test_adjoint_refuses_free_slip_walls():
+    """The adjoint's extension maps cover periodic and no-slip walls only."""
+    import paper_2012_14729_amd as P
+    from paper_2012_14729_amd._lib import LbmError
+    p = WL.ParamSet(nx=32, ny=16, wall_x=2, rho1=1.0, rho2=1.0, sigma=0.01, W=4.0)
+    sim = P.Simulation(p.as_dict(), np.zeros((16, 32), np.float32))
+    with pytest.raises(LbmError) as e:
+        P.Adjoint(sim)
+    assert "free-slip" in str(e.value) or "no-slip" in str(e.value)

@@ -134,6 +134,32 @@ def test_small_grid_box_walls():
         check(p, phi0, None, None, "cpf1", 100)
 
 
+@pytest.mark.parametrize("case", ["slip_x", "bubble_box", "slip_y", "slip_both"])
+def test_free_slip_walls(case):
+    """Free-slip (specular) half-way walls (reading A24): on x with periodic
+    y; on x with no-slip y-walls (the rising-bubble geometry, corners); on y;
+    on both axes.  Drops and bubbles placed against a wall, with gravity,
+    ragged sizes."""
+    forms = {"slip_x": "stf2", "bubble_box": "cpf1", "slip_y": "csf1", "slip_both": "pf2"}
+    if case == "slip_x":
+        p = WL.ParamSet(nx=80, ny=40, wall_x=2, rho1=5.0, rho2=1.0, nu1=0.1, nu2=0.15, sigma=0.01, W=3.0, M=0.1,
+                        tau_h=0.8, gy=-2e-5)
+        phi0 = WL.droplet(80, 40, 9.0, 3.0, xc=6.3, yc=17.6)
+    elif case == "bubble_box":
+        p = WL.ParamSet(nx=72, ny=44, wall_x=2, wall_y=1, rho1=10.0, rho2=1.0, nu1=0.1, nu2=0.1, sigma=0.01, W=3.0,
+                        M=0.1, tau_h=0.8, gy=-3e-5)
+        phi0 = WL.droplet(72, 44, 9.0, 3.0, xc=7.1, yc=8.4, inside=-1.0)
+    elif case == "slip_y":
+        p = WL.ParamSet(nx=70, ny=36, wall_y=2, rho1=3.0, rho2=1.0, nu1=0.1, nu2=0.1, sigma=0.01, W=3.0, M=0.1,
+                        tau_h=0.8, gx=2e-5)
+        phi0 = WL.droplet(70, 36, 8.0, 3.0, xc=30.2, yc=5.3)
+    else:
+        p = WL.ParamSet(nx=66, ny=40, wall_x=2, wall_y=2, rho1=3.0, rho2=1.0, nu1=0.1, nu2=0.2, sigma=0.01, W=3.0,
+                        M=0.1, tau_h=0.8, gx=1e-5, gy=-2e-5)
+        phi0 = WL.droplet(66, 40, 8.0, 3.0, xc=5.2, yc=34.6)
+    check(p, phi0, None, None, forms[case], 250)
+
+
 def test_merging_pair_csf1():
     p = WL.ParamSet(nx=96, ny=64, rho1=10.0, rho2=1.0, nu1=0.1, nu2=0.1, sigma=3e-3, W=4.0, M=0.1, tau_h=0.8)
     phi0 = WL.two_droplets(96, 64, 14.0, 10.0, 2.0, 4.0)
