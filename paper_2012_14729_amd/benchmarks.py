@@ -1,5 +1,13 @@
 """Physics benchmarks of Sec. V run on the GPU path.
 
+Rising bubble (Sec. V.D, Table V): a bubble of radius 0.25 at (0.5, 0.5)
+in a 1 x 2 box, free-slip side walls, no-slip top and bottom, density ratio
+10, viscosity ratio 10, Re = 35, Eo = 10 (Table IV); y_c, v_c and the
+circularity C are followed to t = 3 (in the benchmark's units: lengths in
+box widths, times in seconds with U_g = sqrt(2 R g) = 0.7).
+
+    python -m paper_2012_14729_amd.benchmarks bubble [--res 240] [--forms ...]
+
 Sheared drop (Sec. V.E): a drop of radius R at the centre of a 2H x H
 channel whose walls move at +-U, equal densities and viscosities, Re = 0.1;
 run until the Taylor deformation D settles and compare it with the
@@ -15,13 +23,14 @@ from __future__ import annotations
 import argparse
 import math
 import time
+from typing import Optional
 
 import numpy as np
 import torch
 
 from . import Simulation
-from .diagnostics import taylor_deformation
-from .units import shear_drop_params, taylor_deformation as taylor_theory
+from .diagnostics import bubble_metrics, taylor_deformation
+from .units import rising_bubble_params, shear_drop_params, taylor_deformation as taylor_theory
 
 
 def shear_drop(form: str, Ca: float, R: float = 20.0, H: float = 160.0, nu: float = 1.0 / 6.0, Re: float = 0.1,
@@ -53,20 +62,79 @@ def shear_drop(form: str, Ca: float, R: float = 20.0, H: float = 160.0, nu: floa
                 theory=taylor_theory(Ca, 1.0), nodes=nx * ny)
 
 
+def rising_bubble(form: str, res: int = 240, U_g: float = 0.05, W: Optional[float] = None, M: float = 0.3,
+                  tau_h: float = 1.0, t_end: float = 3.0, samples: int = 60):
+    """The bubble of Sec. V.D on a res x 2 res lattice.  Returns the history
+    [(t, y_c, v_c, C)] in the benchmark's units (y in box widths, v in m/s,
+    t in s) and its extrema y_max, v_max, C_min.
+
+    The paper does not give its lattice parameters.  These defaults keep the
+    STF, CPF-2, PF-1 and CSF runs stable at density ratio 10: U_g = 0.05 (so
+    tau_f = 1.0 at res 240), an interface of W = 8 nodes at res 240 (5 at
+    res 120) and M = 0.3 with tau_h = 1.0.  With W = 4, M = 0.1 and
+    U_g = 0.02 the order parameter overshoots at the rear of the bubble,
+    where the flow compresses the interface, and the run diverges near
+    t = 0.5.  CPF-1 and PF-2 diverge within the first 200 steps at these
+    surface-tension strengths, with or without gravity."""
+    nx, ny = res, 2 * res
+    R = 0.25 * res
+    Eo, Re = 10.0, 35.0
+    if W is None:
+        W = 5.0 if res <= 120 else 8.0
+    p = rising_bubble_params(R=R, Eo=Eo, Mo=Eo ** 3 / Re ** 4, U_g=U_g, rho_ratio=0.1, mu_ratio=0.1, W=W, M=M,
+                             tau_h=tau_h, nx=nx, ny=ny, wall_x=2, wall_y=1)
+    x = np.arange(nx, dtype=np.float64)[None, :].repeat(ny, 0) + 0.5
+    y = np.arange(ny, dtype=np.float64)[:, None].repeat(nx, 1) + 0.5
+    r = np.sqrt((x - 0.5 * res) ** 2 + (y - 0.5 * res) ** 2)
+    phi0 = np.tanh(2.0 * (r - R) / W).astype(np.float32)         # fluid 2 (phi = -1) inside
+    sim = Simulation(p, phi0)
+    L_lat, L_phys, Ug_phys = 2.0 * R, 0.5, 0.7
+    dt = (L_phys / Ug_phys) / (L_lat / U_g)                        # seconds per step
+    total = int(round(t_end / dt))
+    chunk = max(1, total // samples)
+    hist = []
+    n = 0
+    t0 = time.time()
+    while n < total:
+        k = min(chunk, total - n)
+        sim.step(k, form)
+        n += k
+        m = sim.moments(form)
+        if not bool(torch.isfinite(m["phi"]).all()):
+            break                                                   # diverged: report up to here
+        yc, vc, C = bubble_metrics(m["phi"], m["uy"])
+        hist.append((n * dt, yc / res, vc / U_g * Ug_phys, C))
+    torch.cuda.synchronize()
+    return dict(form=form, res=res, history=hist, y_max=max((h[1] for h in hist), default=float("nan")),
+                v_max=max((h[2] for h in hist), default=float("nan")),
+                C_min=min((h[3] for h in hist), default=float("nan")), steps=n, t_reached=n * dt,
+                seconds=time.time() - t0, nodes=nx * ny, diverged=sim.status())
+
+
 def _main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["taylor"])
+    ap.add_argument("which", choices=["taylor", "bubble"])
+    ap.add_argument("--res", type=int, default=240)
+    ap.add_argument("--W", type=float, default=None)
+    ap.add_argument("--tau-h", type=float, default=1.0)
     ap.add_argument("--forms", default="stf1,stf2,cpf1,cpf2,pf1,pf2,csf1,csf2")
     ap.add_argument("--ca", default="0.1,0.2,0.3,0.4")
     ap.add_argument("--R", type=float, default=20.0)
     ap.add_argument("--shear-times", type=float, default=4.0)
-    ap.add_argument("--M", type=float, default=0.1)
+    ap.add_argument("--M", type=float, default=None, help="mobility (default 0.1 taylor, 0.3 bubble)")
     a = ap.parse_args()
+    if a.which == "bubble":
+        for form in a.forms.split(","):
+            r = rising_bubble(form, res=a.res, W=a.W, M=0.3 if a.M is None else a.M, tau_h=a.tau_h)
+            print(f"bubble form={form} res={a.res} y_max={r['y_max']:.4f} v_max={r['v_max']:.4f} "
+                  f"C_min={r['C_min']:.4f} steps={r['steps']} t={r['t_reached']:.2f} "
+                  f"MLUPS={r['nodes'] * r['steps'] / r['seconds'] / 1e6:.0f} diverged={r['diverged']}", flush=True)
+        return
     for Ca in [float(v) for v in a.ca.split(",")]:
         for form in a.forms.split(","):
-            r = shear_drop(form, Ca, R=a.R, H=8 * a.R, M=a.M, shear_times=a.shear_times)
+            r = shear_drop(form, Ca, R=a.R, H=8 * a.R, M=0.1 if a.M is None else a.M, shear_times=a.shear_times)
             h = r["history"]
-            print(f"taylor form={form} Ca={Ca} R={a.R:g} M={a.M:g} D={r['D']:.4f} dD_last={h[-1][1] - h[-2][1]:+.4f} "
+            print(f"taylor form={form} Ca={Ca} R={a.R:g} M={0.1 if a.M is None else a.M:g} D={r['D']:.4f} dD_last={h[-1][1] - h[-2][1]:+.4f} "
                   f"theory={r['theory']:.4f} steps={r['steps']} tE={r['shear_time']:.2f} area={r['area']:.0f} "
                   f"MLUPS={r['nodes'] * r['steps'] / r['seconds'] / 1e6:.0f} diverged={r['diverged']}", flush=True)
 

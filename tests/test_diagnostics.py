@@ -42,3 +42,28 @@ def test_interface_points_lie_on_the_contour():
     v = (phi[y0, x0] * (1 - fx) * (1 - fy) + phi[y0, x0 + 1] * fx * (1 - fy)
          + phi[y0 + 1, x0] * (1 - fx) * fy + phi[y0 + 1, x0 + 1] * fx * fy)
     assert float(v.abs().max()) < 0.05
+
+
+def test_contour_length_of_circle_and_ellipse():
+    ny, nx = 200, 160
+    y = torch.arange(ny, dtype=torch.float64).view(ny, 1)
+    x = torch.arange(nx, dtype=torch.float64).view(1, nx)
+    r = torch.sqrt((x - 80.3) ** 2 + (y - 100.6) ** 2)
+    assert abs(Dg.contour_length(torch.tanh(2 * (r - 30.0) / 4)) - 2 * math.pi * 30.0) < 0.05
+    a, b = 40.0, 20.0
+    rr = torch.sqrt(((x - 80.3) / a) ** 2 + ((y - 100.6) / b) ** 2)
+    h = ((a - b) / (a + b)) ** 2
+    ramanujan = math.pi * (a + b) * (1 + 3 * h / (10 + math.sqrt(4 - 3 * h)))
+    assert abs(Dg.contour_length(torch.tanh(2 * (rr - 1) * math.sqrt(a * b) / 4)) - ramanujan) < 0.05
+
+
+def test_bubble_metrics_of_a_round_bubble():
+    ny, nx = 240, 120
+    y = torch.arange(ny, dtype=torch.float64).view(ny, 1)
+    x = torch.arange(nx, dtype=torch.float64).view(1, nx)
+    r = torch.sqrt((x - 59.5) ** 2 + (y - 70.25) ** 2)
+    phi = torch.tanh(2 * (r - 30.0) / 5.0)          # fluid 2 inside
+    uy = torch.where(phi < 0, torch.full_like(phi, 0.01), torch.zeros_like(phi))
+    yc, vc, C = Dg.bubble_metrics(phi, uy)
+    assert abs(yc - 70.75) < 1e-6                    # node centres at y + 1/2
+    assert abs(vc - 0.01) < 2e-3 and abs(C - 1.0) < 0.005

@@ -1,0 +1,33 @@
+"""End-to-end physics of the GPU path in the rising-bubble box (Sec. V.D):
+free-slip side walls, no-slip top and bottom, density ratio 10, Re = 35,
+Eo = 10, to t = 3 on the 120 x 240 mesh (interface W = 5 nodes, M = 0.3,
+tau_h = 1.0, U_g = 0.05).  The benchmark quantities land near the values the
+paper prints for its 240 x 480 mesh (Table V)."""
+import json
+import os
+
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("form", ["stf2", "cpf2", "pf1", "csf2"])
+def test_rising_bubble_benchmark_quantities(form):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2012_14729_amd.benchmarks import rising_bubble
+    tab = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table5_bubble.json")))["forms"][form]
+    print(f"[bubble] {form} res=120", flush=True)
+    r = rising_bubble(form, res=120)
+    print(f"[bubble]   y_max={r['y_max']:.4f} v_max={r['v_max']:.4f} C_min={r['C_min']:.4f} "
+          f"(Table V {tab['y_max']}, {tab['v_max']}, {tab['C_min']})", flush=True)
+    assert not r["diverged"] and abs(r["t_reached"] - 3.0) < 1e-3
+    assert abs(r["y_max"] - tab["y_max"]) / tab["y_max"] < 0.03
+    assert abs(r["v_max"] - tab["v_max"]) / tab["v_max"] < 0.10
+    assert abs(r["C_min"] - tab["C_min"]) / tab["C_min"] < 0.04
+    # the bubble rises monotonically over the first second and never leaves the box
+    h = r["history"]
+    ys = [y for t, y, v, c in h if t <= 1.0]
+    assert all(b > a for a, b in zip(ys, ys[1:]))
+    assert max(y for _, y, _, _ in h) < 2.0 - 0.25
