@@ -8,6 +8,11 @@ box widths, times in seconds with U_g = sqrt(2 R g) = 0.7).
 
     python -m paper_2012_14729_amd.benchmarks bubble [--res 240] [--forms ...]
 
+Capillary wave (Sec. V.C, Table III): the amplitude of a small standing
+wave against the analytic solution of Eqs. (44)-(46), error E2 of Eq. (47).
+
+    python -m paper_2012_14729_amd.benchmarks capillary [--H 80] [--rho-ratio 0.1]
+
 Sheared drop (Sec. V.E): a drop of radius R at the centre of a 2H x H
 channel whose walls move at +-U, equal densities and viscosities, Re = 0.1;
 run until the Taylor deformation D settles and compare it with the
@@ -29,7 +34,8 @@ import numpy as np
 import torch
 
 from . import Simulation
-from .diagnostics import bubble_metrics, taylor_deformation
+from .diagnostics import bubble_metrics, taylor_deformation, wave_amplitude
+from .theory import capillary_error, capillary_frequency, capillary_wave as capillary_theory
 from .units import rising_bubble_params, shear_drop_params, taylor_deformation as taylor_theory
 
 
@@ -111,9 +117,60 @@ def rising_bubble(form: str, res: int = 240, U_g: float = 0.05, W: Optional[floa
                 seconds=time.time() - t0, nodes=nx * ny, diverged=sim.status())
 
 
+def capillary_wave(form: str, H: int = 80, rho_ratio: float = 1.0, h0: float = 0.01, U_c: float = 0.0125,
+                   W: float = 4.0, M: float = 0.1, tau_h: float = 0.8, samples: int = 200):
+    """The capillary wave of Sec. V.C: an H x 3H box, periodic in x, no-slip
+    walls top and bottom, fluid 1 (density 1) below the interface
+    y = 1.5 H + h0 H cos(k x), fluid 2 (density rho_ratio) above, equal
+    kinematic viscosity, Re = U_c H / nu = 50 and We = rho_1 H U_c^2 / sigma
+    = 1 (U_c = sqrt(sigma / (rho_1 H))).  Runs to t = 25 / w0 and returns the
+    normalised amplitude history h(t)/h0 against theory (Eqs. 44-46) and the
+    time-averaged error E2 (Eq. 47).  h0 (a fraction of H) is not given in
+    the paper: 0.01 H by default."""
+    nx, ny = H, 3 * H
+    Re, We = 50.0, 1.0
+    nu = U_c * H / Re
+    sigma = 1.0 * H * U_c * U_c / We
+    p = dict(nx=nx, ny=ny, wall_y=1, rho1=1.0, rho2=rho_ratio, nu1=nu, nu2=nu, sigma=sigma, W=W, M=M, tau_h=tau_h)
+    k = 2.0 * math.pi / H
+    amp = h0 * H
+    x = np.arange(nx, dtype=np.float64)[None, :].repeat(ny, 0) + 0.5
+    y = np.arange(ny, dtype=np.float64)[:, None].repeat(nx, 1) + 0.5
+    level = 1.5 * H
+    phi0 = np.tanh(2.0 * (level + amp * np.cos(k * x) - y) / W).astype(np.float32)
+    sim = Simulation(p, phi0)
+    w0 = capillary_frequency(k, 1.0, rho_ratio, sigma)
+    total = int(math.ceil(25.0 / w0))
+    # normalise by the amplitude measured on the initial field, so that the
+    # interpolation of the diffuse profile does not bias h(t)/h0
+    a0 = wave_amplitude(sim.moments(form)["phi"], level)
+    hist = [(0.0, 1.0)]
+    n = 0
+    t0 = time.time()
+    for s_ in range(samples):
+        m_ = int(round(total * (s_ + 1) / samples)) - n
+        sim.step(m_, form)
+        n += m_
+        phi = sim.moments(form)["phi"]
+        if not bool(torch.isfinite(phi).all()):
+            break
+        hist.append((n, wave_amplitude(phi, level) / a0))
+    torch.cuda.synchronize()
+    t = np.array([h[0] for h in hist])
+    hn = np.array([h[1] for h in hist])
+    done = n >= total and len(hist) == samples + 1
+    e2 = capillary_error(t, hn, nu, k, 1.0, rho_ratio, sigma) if done else float("nan")
+    return dict(form=form, H=H, rho_ratio=rho_ratio, t=t, h=hn, theory=capillary_theory(t, nu, k, 1.0, rho_ratio, sigma),
+                E2=e2, h0_measured=a0 / amp, steps=n, seconds=time.time() - t0, nodes=nx * ny,
+                diverged=sim.status())
+
+
 def _main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["taylor", "bubble"])
+    ap.add_argument("which", choices=["taylor", "bubble", "capillary"])
+    ap.add_argument("--H", type=int, default=80)
+    ap.add_argument("--rho-ratio", type=float, default=1.0)
+    ap.add_argument("--Uc", type=float, default=0.0125)
     ap.add_argument("--res", type=int, default=240)
     ap.add_argument("--W", type=float, default=None)
     ap.add_argument("--tau-h", type=float, default=1.0)
@@ -123,6 +180,13 @@ def _main():
     ap.add_argument("--shear-times", type=float, default=4.0)
     ap.add_argument("--M", type=float, default=None, help="mobility (default 0.1 taylor, 0.3 bubble)")
     a = ap.parse_args()
+    if a.which == "capillary":
+        for form in a.forms.split(","):
+            r = capillary_wave(form, H=a.H, rho_ratio=a.rho_ratio, U_c=a.Uc, M=0.1 if a.M is None else a.M)
+            print(f"capillary form={form} H={a.H} rho2/rho1={a.rho_ratio:g} Uc={a.Uc:g} M={0.1 if a.M is None else a.M:g} E2={r['E2']:.4f} "
+                  f"h(0)/h0={r['h0_measured']:.4f} steps={r['steps']} "
+                  f"MLUPS={r['nodes'] * r['steps'] / r['seconds'] / 1e6:.0f} diverged={r['diverged']}", flush=True)
+        return
     if a.which == "bubble":
         for form in a.forms.split(","):
             r = rising_bubble(form, res=a.res, W=a.W, M=0.3 if a.M is None else a.M, tau_h=a.tau_h)

@@ -112,3 +112,29 @@ def bubble_metrics(phi: torch.Tensor, uy: torch.Tensor):
     if perim == 0.0:
         raise ValueError("no phi = 0 contour")
     return yc, vc, 2.0 * math.sqrt(math.pi * area) / perim
+
+
+def interface_heights(phi: torch.Tensor):
+    """Height of the phi = 0 level in every column (fluid 1, phi > 0, below):
+    the first downward crossing from the bottom, linearly interpolated, in
+    distance from the lower wall (node j sits at j + 1/2).  Columns with no
+    crossing give NaN."""
+    p = phi.double()
+    ny, nx = p.shape
+    a, b = p[:-1, :], p[1:, :]
+    cross = (a > 0) & (b <= 0)
+    j = torch.argmax(cross.int(), dim=0)                 # first crossing per column
+    has = cross.any(dim=0)
+    cols = torch.arange(nx, device=p.device)
+    pa, pb = a[j, cols], b[j, cols]
+    y = j.double() + 0.5 + pa / (pa - pb)
+    return torch.where(has, y, torch.full_like(y, float("nan")))
+
+
+def wave_amplitude(phi: torch.Tensor, mean_level: float) -> float:
+    """Amplitude of the first Fourier mode of the interface heights about
+    mean_level, for a wave cos(2 pi (i + 1/2) / nx) along x."""
+    y = interface_heights(phi) - mean_level
+    nx = y.numel()
+    x = (torch.arange(nx, dtype=torch.float64, device=y.device) + 0.5) * (2.0 * math.pi / nx)
+    return float(2.0 / nx * (y * torch.cos(x)).sum())
