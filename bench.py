@@ -34,6 +34,7 @@ HBM_PEAK_GBS = 8000.0
 BYTES_FUSED = 9 * 4 + 4 + 8 * 4 + 2 * 4 + 8 + 9 * 4 + 4 + 9 * 4 + 2 * 4
 BYTES_PHI = 4 + 8 * 4 + 8 + 8
 FORMS = ("stf1", "stf2", "cpf1", "cpf2", "pf1", "pf2", "csf1", "csf2")
+TIMING_PERIOD = 8   # kernel durations: HIP events on one step in eight of the timed region
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fused_droplet2048.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2012_14729_amd", "csrc", "lbm_kernels.hip")
 
@@ -222,8 +223,10 @@ def main():
     torch.cuda.synchronize()
     print("[bench] warm-up done", file=sys.stderr, flush=True)
 
+    # the launch durations are sampled on one step in TIMING_PERIOD: events
+    # around every launch would add their own gaps to the timed region
     for s in sims:
-        s.set_timing(True)
+        s.set_timing(True, period=TIMING_PERIOD)
     torch.cuda.synchronize()
     per = args.steps // 8
     t0 = time.perf_counter()

@@ -146,12 +146,15 @@ int lbm_state_bytes(const lbm_sim* sim, size_t* bytes);
 int lbm_save(lbm_sim* sim, void* d_blob, void* stream);
 int lbm_restore(lbm_sim* sim, const void* d_blob, void* stream);
 
-/* Kernel timing with HIP events recorded on the launch stream around every
- * launch of one kernel.  kernel: 0 = fused collide-stream kernel, 1 = order
- * parameter kernel.  lbm_kernel_time synchronises and returns the summed
- * elapsed milliseconds and the number of timed launches since the last reset;
- * enabling resets the counters. */
-int lbm_set_timing(lbm_sim* sim, int32_t enable);
+/* Kernel timing with HIP events recorded on the launch stream around the
+ * launches of one kernel.  period: 0 = off; k >= 1 = time the two launches of
+ * every k-th step (step counter divisible by k), so k > 1 samples the launch
+ * durations with fewer events in the stream.  kernel: 0 = fused
+ * collide-stream kernel, 1 = order parameter kernel.  lbm_kernel_time
+ * synchronises and returns the summed elapsed milliseconds and the number of
+ * timed launches since the last reset; every call of lbm_set_timing drains
+ * the pending events and resets the counters.  LBM_E_INVAL for period < 0. */
+int lbm_set_timing(lbm_sim* sim, int32_t period);
 int lbm_kernel_time(lbm_sim* sim, int32_t kernel, double* total_ms, int64_t* launches);
 
 int lbm_destroy(lbm_sim* sim);

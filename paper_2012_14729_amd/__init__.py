@@ -136,8 +136,9 @@ class Simulation:
     def restore(self, blob, stream=None):
         check(lib().lbm_restore(self._h, _ptr(blob), _stream(stream)))
 
-    def set_timing(self, enable=True):
-        check(lib().lbm_set_timing(self._h, 1 if enable else 0))
+    def set_timing(self, enable=True, period=1):
+        """Time the kernels of every `period`-th step (lbm_set_timing); off if not enable."""
+        check(lib().lbm_set_timing(self._h, int(period) if enable else 0))
 
     def kernel_time(self, kernel=0):
         ms, n = C.c_double(), C.c_int64()

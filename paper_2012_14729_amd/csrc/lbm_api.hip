@@ -307,15 +307,16 @@ int lbm_step(lbm_sim* s, int32_t nsteps, int32_t form, void* stream) {
   for (int32_t n = 0; n < nsteps; ++n) {
     StepArgs a = step_args(s);
     int slot = 0;
-    if (s->timing)
+    const bool timed = s->timing && s->step % s->timing == 0;
+    if (timed)
       if (int r = timer_start(s, 0, st, &slot)) return r;
     HIPCHK(launch_fused(form, a, st));
-    if (s->timing) {
+    if (timed) {
       if (int r = timer_stop(s, 0, slot, st)) return r;
       if (int r = timer_start(s, 1, st, &slot)) return r;
     }
     HIPCHK(launch_phi(a.sout, s->phi(), s->L.g, s->c.wall_x, s->c.wall_y, st));
-    if (s->timing)
+    if (timed)
       if (int r = timer_stop(s, 1, slot, st)) return r;
     s->cur = 1 - s->cur;
     s->step += 1;
@@ -387,6 +388,7 @@ int lbm_restore(lbm_sim* s, const void* d_blob, void* stream) {
 
 int lbm_set_timing(lbm_sim* s, int32_t enable) {
   if (!s) return fail(LBM_E_INVAL, "sim is NULL");
+  if (enable < 0) return fail(LBM_E_INVAL, "timing period must be >= 0");
   if (enable && !s->ev[0][0][0]) {   // create the event ring on first use
     for (int k = 0; k < 2; ++k)
       for (int j = 0; j < lbm_sim::kRing; ++j)
@@ -395,7 +397,7 @@ int lbm_set_timing(lbm_sim* s, int32_t enable) {
   for (int k = 0; k < 2; ++k)
     if (s->ev[0][0][0])
       if (int r = drain_all(s, k)) return r;
-  s->timing = enable ? 1 : 0;
+  s->timing = enable;   // 0: off; k: every k-th step
   s->t_ms[0] = s->t_ms[1] = 0.0;
   s->t_n[0] = s->t_n[1] = 0;
   return LBM_OK;
