@@ -215,8 +215,8 @@ def main():
     sims = [P.Simulation(p.as_dict(), phi0, device=dev) for _ in FORMS]
     cells = p.nx * p.ny
 
-    if args.steps % 8:
-        print("bench.py: --steps must be a multiple of 8 (one run per force form)", file=sys.stderr)
+    if args.steps % 8 or args.steps < 8:
+        print("bench.py: --steps must be a positive multiple of 8 (one run per force form)", file=sys.stderr)
         sys.exit(2)
     for k, (s, f) in enumerate(zip(sims, FORMS)):
         s.step(max(1, args.warmup // 8), f)
@@ -224,11 +224,12 @@ def main():
     print("[bench] warm-up done", file=sys.stderr, flush=True)
 
     # the launch durations are sampled on one step in TIMING_PERIOD: events
-    # around every launch would add their own gaps to the timed region
-    for s in sims:
-        s.set_timing(True, period=TIMING_PERIOD)
-    torch.cuda.synchronize()
+    # around every launch would add their own gaps to the timed region.  A
+    # period no longer than the steps each form runs times at least one of them.
     per = args.steps // 8
+    for s in sims:
+        s.set_timing(True, period=min(TIMING_PERIOD, per))
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s, f in zip(sims, FORMS):
         for _ in range(per):
@@ -259,7 +260,9 @@ def main():
         torch.cuda.synchronize()
         per_form[f] = round(cells * nper / (time.perf_counter() - t1) / 1e6, 1)
 
-    fused_avg_s = fused_ms / max(fused_n, 1) / 1e3
+    if fused_n == 0 or phi_n == 0:
+        raise RuntimeError("no kernel launch was timed")
+    fused_avg_s = fused_ms / fused_n / 1e3
     achieved = BYTES_FUSED * cells / fused_avg_s / 1e9
     traffic = measured_traffic()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -875,8 +875,18 @@ __global__ __launch_bounds__(256) void k_init_local(const float* __restrict__ ph
                                                     float* __restrict__ s0, double* __restrict__ phi, Grid g, Phys c) {
   const int x = blockIdx.x * 64 + (threadIdx.x & 63);
   const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (x >= g.nx || y >= g.ny) return;
+  if (x >= g.pitch || y >= g.ny) return;
   const unsigned on = nbase(g, x, y);
+  if (x >= g.nx) {
+    // lanes past nx in the last 64-node segment of a row: no step writes
+    // them, so they are zeroed here (equal states then save to equal blobs)
+    for (int k = 0; k < kNPL; ++k) {
+      s_tmp[on + (unsigned)(k * 64)] = 0.0f;
+      s0[on + (unsigned)(k * 64)] = 0.0f;
+    }
+    phi[(long long)y * g.pitch + x] = 0.0;
+    return;
+  }
   const double p0 = (double)phi0[(long long)y * g.nx + x];
   double sl = 0.0;
 #pragma unroll
