@@ -107,7 +107,10 @@ def bench_batched(steps, loop_steps):
     b.step(steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    unstable = sum(b.status())
+    flags = list(b.status())
+    unstable = [{"instance": k, "side": params[k]["nx"], "form": FORMS[forms[k]],
+                 "rho_ratio": params[k]["rho1"] / params[k]["rho2"], "sigma": float(f"{params[k]['sigma']:.4g}")}
+                for k, fl in enumerate(flags) if fl]
     del b
     torch.cuda.empty_cache()
     sims = [P.Simulation(pp, x) for pp, x in zip(params, phis)]
@@ -126,7 +129,8 @@ def bench_batched(steps, loop_steps):
     loop = cells * loop_steps / el_loop / 1e6
     return {"MLUPS": round(batched, 1), "instances": 512, "nodes": cells, "steps": steps,
             "looping_plain_lbm_step_MLUPS": round(loop, 1), "loop_steps": loop_steps,
-            "speedup_vs_loop": round(batched / loop, 2), "unstable_instances": unstable,
+            "speedup_vs_loop": round(batched / loop, 2), "unstable_instances": len(unstable),
+            "unstable": unstable,
             "launch_shape": {"one_kernel_per_form": bool(shape["split"]), "interior_path": bool(shape["fast"]),
                              "workgroups_per_cu": shape["blocks_per_cu"] or "one per tile",
                              "tuned_ms_per_step": round(shape["ms_per_step"], 4)},
