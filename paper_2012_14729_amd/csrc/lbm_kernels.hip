@@ -486,13 +486,25 @@ __device__ __forceinline__ void store_pair(const StepArgs& a, int x, int y, unsi
   }
 }
 
+// The thread index of a tile body.  A persistent kernel runs the body in a
+// loop (LOOPED); there the compiler would hoist every value derived from the
+// index out of the loop and hold it across the whole body (spills at the
+// 128 VGPRs of four waves per SIMD).  An index it cannot see through is
+// recomputed per tile instead.
+template <bool LOOPED>
+__device__ __forceinline__ int tile_tid() {
+  int t = threadIdx.x;
+  if constexpr (LOOPED) asm volatile("" : "+v"(t));
+  return t;
+}
+
 // One 64x8 tile of the step (or of the moments): the whole per-node update
 // of a1-a12.  FAST: an interior tile (see interior_tile), step only.
-template <int FORM, bool MOMENTS, int BC, bool FAST>
+template <int FORM, bool MOMENTS, int BC, bool FAST, bool LOOPED = false>
 __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const MomentArgs& m, int tile_x, int tile_y) {
   static_assert(!(FAST && MOMENTS), "the moments use the general path");
   constexpr bool WX = (BC & 1) != 0, WY = (BC & 2) != 0;   // walled axes (compile time)
-  const int tid = threadIdx.x;
+  const int tid = tile_tid<LOOPED>();
   const int x0 = tile_x * kTX, y0 = tile_y * kTY;
   const int lx = tid & (kTX - 1), ty = tid / kTX;   // one node per thread
   const Grid& g = a.g;
@@ -520,7 +532,13 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
   // first, so they arrive while the order parameter is staged.
   float ft[9], ps[9], h[9];
   float j0 = 0.f, j1 = 0.f;
+  // Only ring threads define these.  The others start from a kernel
+  // argument, not a constant: with a constant there the compiler moves the
+  // FP64 conversions of the ring values up to their loads, and the ring
+  // threads then wait for those loads before staging the order parameter.
   float rft[9], rps[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) rft[i] = rps[i] = c.gx;
   int ruy = 0, rux = 0;
   if constexpr (FAST && !MOMENTS) {
     if (tid < NRING) {
@@ -532,11 +550,15 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
   }
   // Stage A: phi tile with a 3-node halo (periodic wrap / even reflection at walls, Sec. IV)
   if constexpr (FAST) {
+    // both loads of a thread in flight before either is stored
+    static_assert(PH * PW > kFusedThreads && PH * PW <= 2 * kFusedThreads, "two phi values per thread");
     const double* tphi = a.phi + ((long long)(y0 - 3) * g.pitch + (x0 - 3));
-    for (int k = tid; k < PH * PW; k += kFusedThreads) {
-      const int py = k / PW, px = k - py * PW;
-      s.phi[py][px] = *at(tphi, (unsigned)(py * g.pitch + px) * 8u);
-    }
+    const int k1 = tid + kFusedThreads;
+    const int py0 = tid / PW, px0 = tid - py0 * PW, py1 = k1 / PW, px1 = k1 - py1 * PW;
+    const double p0 = *at(tphi, (unsigned)(py0 * g.pitch + px0) * 8u);
+    const double p1 = k1 < PH * PW ? *at(tphi, (unsigned)(py1 * g.pitch + px1) * 8u) : 0.0;
+    s.phi[py0][px0] = p0;
+    if (k1 < PH * PW) s.phi[py1][px1] = p1;
   } else {
     for (int k = tid; k < PH * PW; k += kFusedThreads) {
       const int py = k / PW, px = k - py * PW;
@@ -555,6 +577,10 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
   // forms, so their latency overlaps the ring's work (measured: no gain for
   // the CSF forms, and the stress forms need those registers for the ring).
   constexpr bool kEarlyOwn = FAST && FORM >= 2 && FORM <= 5;
+  // The same forms also request their h and (phi u) pulls before the last
+  // barrier (measured: CPF and PF -1 to -2 us; the stress and CSF forms
+  // would spill or slow down).
+  constexpr bool kEarlyH = kEarlyOwn;
   unsigned v3[3] = {0u, 0u, 0u};
   if constexpr (FAST) node_offsets(g, x0, lx, ty, v3);
   if constexpr (kEarlyOwn) load_fp_tile<true>(tin, g.rowe, v3, ft, ps);
@@ -599,9 +625,7 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
     }
     return;
   } else {
-    __syncthreads();
-    if (!act) return;
-    if constexpr (FAST) {
+    if constexpr (kEarlyH) {
       h[1] = pull_tile<1, kPH + 1, true>(tin, g.rowe, v3);
       h[2] = pull_tile<2, kPH + 2, true>(tin, g.rowe, v3);
       h[3] = pull_tile<3, kPH + 3, true>(tin, g.rowe, v3);
@@ -612,7 +636,21 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
       h[8] = pull_tile<8, kPH + 8, true>(tin, g.rowe, v3);
       j0 = pull_tile<0, kPJ, true>(tin, g.rowe, v3);
       j1 = pull_tile<0, kPJ + 1, true>(tin, g.rowe, v3);
-    } else {
+    }
+    __syncthreads();
+    if (!act) return;
+    if constexpr (FAST && !kEarlyH) {
+      h[1] = pull_tile<1, kPH + 1, true>(tin, g.rowe, v3);
+      h[2] = pull_tile<2, kPH + 2, true>(tin, g.rowe, v3);
+      h[3] = pull_tile<3, kPH + 3, true>(tin, g.rowe, v3);
+      h[4] = pull_tile<4, kPH + 4, true>(tin, g.rowe, v3);
+      h[5] = pull_tile<5, kPH + 5, true>(tin, g.rowe, v3);
+      h[6] = pull_tile<6, kPH + 6, true>(tin, g.rowe, v3);
+      h[7] = pull_tile<7, kPH + 7, true>(tin, g.rowe, v3);
+      h[8] = pull_tile<8, kPH + 8, true>(tin, g.rowe, v3);
+      j0 = pull_tile<0, kPJ, true>(tin, g.rowe, v3);
+      j1 = pull_tile<0, kPJ + 1, true>(tin, g.rowe, v3);
+    } else if constexpr (!FAST) {
       constexpr int wx = WX, wy = WY;
 #define PULL_HG(I)                                                 \
   {                                                                \
@@ -734,15 +772,15 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
   }
 }
 
-template <int FORM, bool MOMENTS, int BC>
+template <int FORM, bool MOMENTS, int BC, bool LOOPED = false>
 __device__ __forceinline__ void fused_tile(Lds& s, const StepArgs& a, const MomentArgs& m, int tile_x, int tile_y) {
   if constexpr (!MOMENTS) {
     if (interior_tile(tile_x * kTX, tile_y * kTY, a.g)) {
-      tile_impl<FORM, false, BC, true>(s, a, m, tile_x, tile_y);
+      tile_impl<FORM, false, BC, true, LOOPED>(s, a, m, tile_x, tile_y);
       return;
     }
   }
-  tile_impl<FORM, MOMENTS, BC, false>(s, a, m, tile_x, tile_y);
+  tile_impl<FORM, MOMENTS, BC, false, LOOPED>(s, a, m, tile_x, tile_y);
 }
 
 template <int FORM, bool MOMENTS, int BC>
@@ -822,8 +860,8 @@ __device__ __forceinline__ void band(int t0, int t1, int& first, int& end, int& 
 // general one.
 template <int FORM, bool FAST_OK>
 __device__ __forceinline__ void batch_tile(Lds& s, const StepArgs& a, int tx, int ty) {
-  if constexpr (FAST_OK) fused_tile<FORM, false, 0>(s, a, MomentArgs{}, tx, ty);
-  else tile_impl<FORM, false, 0, false>(s, a, MomentArgs{}, tx, ty);
+  if constexpr (FAST_OK) fused_tile<FORM, false, 0, true>(s, a, MomentArgs{}, tx, ty);
+  else tile_impl<FORM, false, 0, false, true>(s, a, MomentArgs{}, tx, ty);
 }
 
 // FORM >= 0: every tile of [t0, t1) has that force form (the tile list is
