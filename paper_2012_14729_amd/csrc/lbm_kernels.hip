@@ -529,25 +529,19 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
   // This node's flow populations are pulled after the ring velocities (the
   // ring threads would otherwise hold both sets of registers at once).  On
   // interior tiles the ring threads request their ring node's populations
-  // first, so they arrive while the order parameter is staged.
+  // right after staging the order parameter, so those loads are in flight
+  // through the first barrier and the stencil stage: nothing waits for
+  // them before the ring's velocities.
   float ft[9], ps[9], h[9];
   float j0 = 0.f, j1 = 0.f;
   // Only ring threads define these.  The others start from a kernel
   // argument, not a constant: with a constant there the compiler moves the
   // FP64 conversions of the ring values up to their loads, and the ring
-  // threads then wait for those loads before staging the order parameter.
+  // threads then wait for those loads as soon as they are issued.
   float rft[9], rps[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) rft[i] = rps[i] = c.gx;
   int ruy = 0, rux = 0;
-  if constexpr (FAST && !MOMENTS) {
-    if (tid < NRING) {
-      ring_pos(tid, ruy, rux);
-      unsigned rv[3];
-      node_offsets(g, x0, rux - 1, ruy - 1, rv);
-      load_fp_tile<false>(tin, g.rowe, rv, rft, rps);
-    }
-  }
   // Stage A: phi tile with a 3-node halo (periodic wrap / even reflection at walls, Sec. IV)
   if constexpr (FAST) {
     // both loads of a thread in flight before either is stored
@@ -559,6 +553,14 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
     const double p1 = k1 < PH * PW ? *at(tphi, (unsigned)(py1 * g.pitch + px1) * 8u) : 0.0;
     s.phi[py0][px0] = p0;
     if (k1 < PH * PW) s.phi[py1][px1] = p1;
+    if constexpr (!MOMENTS) {
+      if (tid < NRING) {
+        ring_pos(tid, ruy, rux);
+        unsigned rv[3];
+        node_offsets(g, x0, rux - 1, ruy - 1, rv);
+        load_fp_tile<false>(tin, g.rowe, rv, rft, rps);
+      }
+    }
   } else {
     for (int k = tid; k < PH * PW; k += kFusedThreads) {
       const int py = k / PW, px = k - py * PW;
