@@ -542,6 +542,7 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
 #pragma unroll
   for (int i = 0; i < 9; ++i) rft[i] = rps[i] = c.gx;
   int ruy = 0, rux = 0;
+  bool ring_ok = true;   // general path: the ring position is not beyond a wall
   // Stage A: phi tile with a 3-node halo (periodic wrap / even reflection at walls, Sec. IV)
   if constexpr (FAST) {
     // both loads of a thread in flight before either is stored
@@ -562,11 +563,24 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
       }
     }
   } else {
-    for (int k = tid; k < PH * PW; k += kFusedThreads) {
-      const int py = k / PW, px = k - py * PW;
-      const int gx = halo_coord<WX>(x0 + px - 3, g.nx);
-      const int gy = halo_coord<WY>(y0 + py - 3, g.ny);
-      s.phi[py][px] = a.phi[(unsigned)(gy * g.pitch + gx)];
+    // the same order as on interior tiles: both phi loads, the stores, then
+    // the ring's pulls, which stay in flight through the stencil stage
+    const int k1 = tid + kFusedThreads;
+    const int py0 = tid / PW, px0 = tid - py0 * PW, py1 = k1 / PW, px1 = k1 - py1 * PW;
+    const double p0 =
+        a.phi[(unsigned)(halo_coord<WY>(y0 + py0 - 3, g.ny) * g.pitch + halo_coord<WX>(x0 + px0 - 3, g.nx))];
+    const double p1 = k1 < PH * PW ? a.phi[(unsigned)(halo_coord<WY>(y0 + py1 - 3, g.ny) * g.pitch +
+                                                      halo_coord<WX>(x0 + px1 - 3, g.nx))]
+                                   : 0.0;
+    s.phi[py0][px0] = p0;
+    if (k1 < PH * PW) s.phi[py1][px1] = p1;
+    if constexpr (!MOMENTS) {
+      if (tid < NRING) {
+        ring_pos(tid, ruy, rux);
+        int rx, ry;
+        ring_ok = ring_global<WX, WY>(ruy, rux, x0, y0, a, rx, ry);
+        if (ring_ok) load_fp<WX, WY>(a, rx, ry, rft, rps);
+      }
     }
   }
   __syncthreads();
@@ -588,14 +602,7 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
   if constexpr (kEarlyOwn) load_fp_tile<true>(tin, g.rowe, v3, ft, ps);
   if constexpr (!MOMENTS) {
     if (tid < NRING) {
-      bool ok = true;
-      if constexpr (!FAST) {
-        ring_pos(tid, ruy, rux);
-        int rx, ry;
-        ok = ring_global<WX, WY>(ruy, rux, x0, y0, a, rx, ry);
-        if (ok) load_fp<WX, WY>(a, rx, ry, rft, rps);
-      }
-      if (ok) {
+      if (FAST || ring_ok) {
         NodeState rs;
         velocity_from<FORM, false>(s, a, ruy, rux, rft, rps, rs);
         const double ph = s.phi[ruy + 2][rux + 2];
