@@ -96,7 +96,7 @@ struct ACon {
 // Physical pre-collision state from the stored single-lattice state (pull
 // form of streaming, Eq. 43 pre-applied): f_i = ft_i + w_i P at the source,
 // h_i pulled for i >= 1, h_0 = phi - sum_{i>=1} h_i, J.
-__global__ void k_adj_unpack(const float* __restrict__ S, const double* __restrict__ phis, AGrid g, ABuf b) {
+__global__ __launch_bounds__(kB) void k_adj_unpack(const float* __restrict__ S, const double* __restrict__ phis, AGrid g, ABuf b) {
   const int k = blockIdx.x * kB + threadIdx.x;
   if (k >= g.nx * g.ny) return;
   const int x = k % g.nx, y = k / g.nx;
@@ -122,7 +122,7 @@ __global__ void k_adj_unpack(const float* __restrict__ S, const double* __restri
   b.J[N + k] = (double)S[on + (unsigned)((kPJ + 1) * 64)];
 }
 
-__global__ void k_adj_fa(AGrid g, ABuf b) {   // phi = sum_i h_i (Eq. 37), then the e2 extension
+__global__ __launch_bounds__(kB) void k_adj_fa(AGrid g, ABuf b) {   // phi = sum_i h_i (Eq. 37), then the e2 extension
   const int ne = (g.nx + 4) * (g.ny + 4);
   const int k = blockIdx.x * kB + threadIdx.x;
   if (k >= ne) return;
@@ -137,7 +137,7 @@ __global__ void k_adj_fa(AGrid g, ABuf b) {   // phi = sum_i h_i (Eq. 37), then 
 }
 
 // On e1: grad, lap (Eqs. 41-42), mu_phi (Eq. 2) and the form's node fields.
-__global__ void k_adj_fb(AGrid g, ACon c, ABuf b) {
+__global__ __launch_bounds__(kB) void k_adj_fb(AGrid g, ACon c, ABuf b) {
   const int ne = (g.nx + 2) * (g.ny + 2);
   const int k = blockIdx.x * kB + threadIdx.x;
   if (k >= ne) return;
@@ -168,7 +168,7 @@ __global__ void k_adj_fb(AGrid g, ACon c, ABuf b) {
 }
 
 // Interior: F_sf (Sec. II.B), F_g (Eq. 8), rho, mu, tau_f (A6), u and P (Eq. 37), Q = phi u.
-__global__ void k_adj_fc(AGrid g, ACon c, ABuf b) {
+__global__ __launch_bounds__(kB) void k_adj_fc(AGrid g, ACon c, ABuf b) {
   const int N = g.nx * g.ny;
   const int k = blockIdx.x * kB + threadIdx.x;
   if (k >= N) return;
@@ -233,7 +233,7 @@ __global__ void k_adj_fc(AGrid g, ACon c, ABuf b) {
 }
 
 // e1: ghost velocity (A9) and the node field phi u for div(phi u).
-__global__ void k_adj_fd(AGrid g, ACon c, ABuf b) {
+__global__ __launch_bounds__(kB) void k_adj_fd(AGrid g, ACon c, ABuf b) {
   const int ne = (g.nx + 2) * (g.ny + 2), N = g.nx * g.ny;
   const int k = blockIdx.x * kB + threadIdx.x;
   if (k >= ne) return;
@@ -249,7 +249,7 @@ __global__ void k_adj_fd(AGrid g, ACon c, ABuf b) {
   b.Q1[k] = ph * ux; b.Q1[ne + k] = ph * uy;
 }
 
-__global__ void k_adj_fe(AGrid g, ABuf b) {   // D = div(phi u) (Eq. 41), dQ = Q - J (A4)
+__global__ __launch_bounds__(kB) void k_adj_fe(AGrid g, ABuf b) {   // D = div(phi u) (Eq. 41), dQ = Q - J (A4)
   const int N = g.nx * g.ny, ne = (g.nx + 2) * (g.ny + 2);
   const int k = blockIdx.x * kB + threadIdx.x;
   if (k >= N) return;
@@ -272,7 +272,7 @@ __global__ void k_adj_fe(AGrid g, ABuf b) {   // D = div(phi u) (Eq. 41), dQ = Q
 // lam: lambda_{n+1} (9 f, 9 h, 2 J planes).  Writes the partial adjoints of
 // the pre-collision populations and of every node quantity they depend on.
 // lam and lam_out may be the same array (in-place step): not restrict-qualified.
-__global__ void k_adj_b1(AGrid g, ACon c, ABuf b, const double* lam, double* lam_out) {
+__global__ __launch_bounds__(kB) void k_adj_b1(AGrid g, ACon c, ABuf b, const double* lam, double* lam_out) {
   const int N = g.nx * g.ny;
   const int k = blockIdx.x * kB + threadIdx.x;
   if (k >= N) return;
@@ -366,7 +366,7 @@ __global__ void k_adj_b1(AGrid g, ACon c, ABuf b, const double* lam, double* lam
 }
 
 // e1: transpose of D = div(Q1) and of Q1 = phi_e1 u_e1.
-__global__ void k_adj_b2(AGrid g, ABuf b) {
+__global__ __launch_bounds__(kB) void k_adj_b2(AGrid g, ABuf b) {
   const int ne = (g.nx + 2) * (g.ny + 2);
   const int k = blockIdx.x * kB + threadIdx.x;
   if (k >= ne) return;
@@ -387,7 +387,7 @@ __global__ void k_adj_b2(AGrid g, ABuf b) {
 
 // Interior: fold the ghost-velocity adjoints back (A9), then transpose
 // u = (j + cs^2 F/2)/(cs^2 rho), P's S = sum f, F = F_sf + (rho - rho0) g, rho(phi).
-__global__ void k_adj_b3(AGrid g, ACon c, ABuf b) {
+__global__ __launch_bounds__(kB) void k_adj_b3(AGrid g, ACon c, ABuf b) {
   const int N = g.nx * g.ny, ne = (g.nx + 2) * (g.ny + 2);
   const int k = blockIdx.x * kB + threadIdx.x;
   if (k >= N) return;
@@ -440,7 +440,7 @@ __global__ void k_adj_b3(AGrid g, ACon c, ABuf b) {
 
 // e1: adjoints of the e1 node fields G1, L1, mu1 from the force (per form),
 // from grad rho and from h^eq.
-__global__ void k_adj_b4(AGrid g, ACon c, ABuf b) {
+__global__ __launch_bounds__(kB) void k_adj_b4(AGrid g, ACon c, ABuf b) {
   const int ne = (g.nx + 2) * (g.ny + 2), N = g.nx * g.ny;
   const int k = blockIdx.x * kB + threadIdx.x;
   if (k >= ne) return;
@@ -531,7 +531,7 @@ __global__ void k_adj_b4(AGrid g, ACon c, ABuf b) {
 }
 
 // e2: transposes of G1 = grad(phie2), L1 = lap(phie2), plus the e1 phi adjoints.
-__global__ void k_adj_b6(AGrid g, ABuf b) {
+__global__ __launch_bounds__(kB) void k_adj_b6(AGrid g, ABuf b) {
   const int n2 = (g.nx + 4) * (g.ny + 4), ne = (g.nx + 2) * (g.ny + 2);
   const int k = blockIdx.x * kB + threadIdx.x;
   if (k >= n2) return;
@@ -554,7 +554,7 @@ __global__ void k_adj_b6(AGrid g, ABuf b) {
 
 // Interior: fold the e2 adjoint of phi back (transpose of the extension) and
 // add it to every h_i (phi = sum_i h_i); write lambda_n.
-__global__ void k_adj_b7(AGrid g, ABuf b, double* __restrict__ lam_out) {
+__global__ __launch_bounds__(kB) void k_adj_b7(AGrid g, ABuf b, double* __restrict__ lam_out) {
   const int N = g.nx * g.ny;
   const int k = blockIdx.x * kB + threadIdx.x;
   if (k >= N) return;
@@ -570,7 +570,7 @@ __global__ void k_adj_b7(AGrid g, ABuf b, double* __restrict__ lam_out) {
   }
 }
 
-__global__ void k_adj_fa_init(AGrid g, const float* __restrict__ phi0, double* __restrict__ phie2) {
+__global__ __launch_bounds__(kB) void k_adj_fa_init(AGrid g, const float* __restrict__ phi0, double* __restrict__ phie2) {
   const int ne = (g.nx + 4) * (g.ny + 4);
   const int k = blockIdx.x * kB + threadIdx.x;
   if (k >= ne) return;
@@ -582,7 +582,7 @@ __global__ void k_adj_fa_init(AGrid g, const float* __restrict__ phi0, double* _
 
 // Adjoint of the initial state (A11): f = f^eq(0, rho(phi0), u0),
 // h = h^eq(phi0, mu(phi0), u0), J = phi0 u0.  Step 1: node-local part.
-__global__ void k_adj_init_a(AGrid g, ACon c, ABuf b, const float* __restrict__ phi0, const float* __restrict__ ux0,
+__global__ __launch_bounds__(kB) void k_adj_init_a(AGrid g, ACon c, ABuf b, const float* __restrict__ phi0, const float* __restrict__ ux0,
                              const float* __restrict__ uy0, const double* __restrict__ lam) {
   const int N = g.nx * g.ny, ne = (g.nx + 2) * (g.ny + 2);
   const int k = blockIdx.x * kB + threadIdx.x;
@@ -608,7 +608,7 @@ __global__ void k_adj_init_a(AGrid g, ACon c, ABuf b, const float* __restrict__ 
 }
 
 // Step 2 (e1 grid first ring + interior): mu0 = 4 beta phi (phi^2-1) - kappa lap(phi0_e1)
-__global__ void k_adj_init_b(AGrid g, ACon c, ABuf b) {
+__global__ __launch_bounds__(kB) void k_adj_init_b(AGrid g, ACon c, ABuf b) {
   const int ne = (g.nx + 2) * (g.ny + 2);
   const int k = blockIdx.x * kB + threadIdx.x;
   if (k >= ne) return;
@@ -632,7 +632,7 @@ __global__ void k_adj_init_b(AGrid g, ACon c, ABuf b) {
 }
 
 // Step 3: transposed Laplacian onto e1 positions, folded onto the nodes.
-__global__ void k_adj_init_c(AGrid g, ABuf b, double* __restrict__ dphi0) {
+__global__ __launch_bounds__(kB) void k_adj_init_c(AGrid g, ABuf b, double* __restrict__ dphi0) {
   const int N = g.nx * g.ny;
   const int k = blockIdx.x * kB + threadIdx.x;
   if (k >= N) return;
@@ -655,12 +655,12 @@ __global__ void k_adj_init_c(AGrid g, ABuf b, double* __restrict__ dphi0) {
   dphi0[k] = acc;
 }
 
-__global__ void k_adj_zero(double* p, long long n) {
+__global__ __launch_bounds__(kB) void k_adj_zero(double* p, long long n) {
   const long long k = (long long)blockIdx.x * kB + threadIdx.x;
   if (k < n) p[k] = 0.0;
 }
 
-__global__ void k_adj_sum(const double* __restrict__ a, long long n, double* out) {   // one block
+__global__ __launch_bounds__(kB) void k_adj_sum(const double* __restrict__ a, long long n, double* out) {   // one block
   __shared__ double red[kB];
   double s = 0;
   for (long long k = threadIdx.x; k < n; k += kB) s += a[k];
@@ -673,7 +673,7 @@ __global__ void k_adj_sum(const double* __restrict__ a, long long n, double* out
   if (threadIdx.x == 0) *out = red[0];
 }
 
-__global__ void k_adj_seed(AGrid g, const double* __restrict__ phi, const float* __restrict__ target,
+__global__ __launch_bounds__(kB) void k_adj_seed(AGrid g, const double* __restrict__ phi, const float* __restrict__ target,
                            double* __restrict__ lam, double* __restrict__ lossd) {
   const int N = g.nx * g.ny;
   const int k = blockIdx.x * kB + threadIdx.x;
