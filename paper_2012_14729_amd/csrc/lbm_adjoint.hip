@@ -407,7 +407,13 @@ __global__ __launch_bounds__(kB) void k_adj_b3(AGrid g, ACon c, ABuf b) {
   double lFx = b.lF[k] + 0.5 * lux / rho, lFy = b.lF[N + k] + 0.5 * luy / rho;
   double lrho = b.lrho[k] - (ux * lux + uy * luy) / rho;
   const double lS = b.lP[k];
-  for (int i = 0; i < 9; ++i) b.lf[(size_t)i * N + k] += cx(i) * ljx + cy(i) * ljy + lS;
+  // all nine planes read before any is written (the compiler cannot tell
+  // the planes apart, so interleaved updates would wait one at a time)
+  double lfv[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) lfv[i] = b.lf[(size_t)i * N + k];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) b.lf[(size_t)i * N + k] = lfv[i] + (cx(i) * ljx + cy(i) * ljy + lS);
   lrho += c.gx * lFx + c.gy * lFy;
   b.lF[k] = lFx; b.lF[N + k] = lFy;   // now the adjoint of F_sf
   double lphi = b.lphi[k] + c.drho_h * lrho;
@@ -459,10 +465,14 @@ __global__ __launch_bounds__(kB) void k_adj_b4(AGrid g, ACon c, ABuf b) {
     // F(x) = 3 sum_i w_i [c_ix T(x + c_i) ; ...]: transpose gathers from x = e - c_i
     double ltxx = 0, ltxy = 0, ltyy = 0;
     for (int i = 1; i < 9; ++i) {
+      // out-of-range neighbours load node 0 and contribute zero, so all
+      // loads are issued together instead of one branch at a time
       const int x = ex - cx(i), y = ey - cy(i);
-      if (x < 0 || x >= g.nx || y < 0 || y >= g.ny) continue;
+      const bool ok = x >= 0 && x < g.nx && y >= 0 && y < g.ny;
+      const int m = ok ? i0(g, x, y) : 0;
       const double w = 3.0 * wtd(i);
-      const double ax = b.lF[i0(g, x, y)], ay = b.lF[N + i0(g, x, y)];
+      const double lx = b.lF[m], ly = b.lF[N + m];
+      const double ax = ok ? lx : 0.0, ay = ok ? ly : 0.0;
       ltxx += w * cx(i) * ax;
       ltxy += w * (cy(i) * ax + cx(i) * ay);
       ltyy += w * cy(i) * ay;
@@ -479,9 +489,10 @@ __global__ __launch_bounds__(kB) void k_adj_b4(AGrid g, ACon c, ABuf b) {
     double acc = 0;
     for (int i = 1; i < 9; ++i) {
       const int x = ex - cx(i), y = ey - cy(i);
-      if (x < 0 || x >= g.nx || y < 0 || y >= g.ny) continue;
-      const int m = i0(g, x, y);
-      acc += 3.0 * wtd(i) * (cx(i) * b.lF[m] + cy(i) * b.lF[N + m]) * b.phi[m];
+      const bool ok = x >= 0 && x < g.nx && y >= 0 && y < g.ny;
+      const int m = ok ? i0(g, x, y) : 0;
+      const double lx = b.lF[m], ly = b.lF[N + m], pm = b.phi[m];
+      acc += 3.0 * wtd(i) * (cx(i) * (ok ? lx : 0.0) + cy(i) * (ok ? ly : 0.0)) * pm;
     }
     if (c.form == 2) lmu += -acc;
     else ll += c.kappa * acc;
@@ -497,8 +508,9 @@ __global__ __launch_bounds__(kB) void k_adj_b4(AGrid g, ACon c, ABuf b) {
     double lnx = 0, lny = 0;
     for (int i = 1; i < 9; ++i) {
       const int x = ex - cx(i), y = ey - cy(i);
-      if (x < 0 || x >= g.nx || y < 0 || y >= g.ny) continue;
-      const double ld = 3.0 * wtd(i) * b.lD[i0(g, x, y)];
+      const bool ok = x >= 0 && x < g.nx && y >= 0 && y < g.ny;
+      const double v = b.lD[ok ? i0(g, x, y) : 0];
+      const double ld = 3.0 * wtd(i) * (ok ? v : 0.0);
       lnx += cx(i) * ld;
       lny += cy(i) * ld;
     }
