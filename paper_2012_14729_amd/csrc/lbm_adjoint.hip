@@ -101,19 +101,29 @@ __global__ __launch_bounds__(kB) void k_adj_unpack(const float* __restrict__ S, 
   if (k >= g.nx * g.ny) return;
   const int x = k % g.nx, y = k / g.nx;
   const int N = g.nx * g.ny;
-  double hsum = 0.0;
+  // every pull is loaded before any result is stored, so the loads are in
+  // flight together (the source of a pull is one node away: one wrap)
+  float fv[9], pv[9], hv[9];
+#pragma unroll
   for (int i = 0; i < 9; ++i) {
     int sx = x - cx(i), sy = y - cy(i), slot = i;
     bool bounce = false;
-    if (sx < 0 || sx >= g.nx) { if (g.wx) bounce = true; else sx = (sx + g.nx) % g.nx; }
-    if (sy < 0 || sy >= g.ny) { if (g.wy) bounce = true; else sy = (sy + g.ny) % g.ny; }
+    if (sx < 0 || sx >= g.nx) { if (g.wx) bounce = true; else sx = sx < 0 ? sx + g.nx : sx - g.nx; }
+    if (sy < 0 || sy >= g.ny) { if (g.wy) bounce = true; else sy = sy < 0 ? sy + g.ny : sy - g.ny; }
     const unsigned nb = bounce ? nbase(g.sg, x, y) : nbase(g.sg, sx, sy);
     if (bounce) slot = opp(i);
-    b.f[(size_t)i * N + k] = (double)S[nb + (unsigned)((kPF + slot) * 64)] + wtd(i) * (double)S[nb + (unsigned)(kPP * 64)];
+    fv[i] = S[nb + (unsigned)((kPF + slot) * 64)];
+    pv[i] = S[nb + (unsigned)(kPP * 64)];
+    hv[i] = i > 0 ? S[nb + (unsigned)((kPH + slot) * 64)] : 0.0f;
+  }
+  double hsum = 0.0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    b.f[(size_t)i * N + k] = (double)fv[i] + wtd(i) * (double)pv[i];
     if (i > 0) {
-      const double hv = (double)S[nb + (unsigned)((kPH + slot) * 64)];
-      b.h[(size_t)i * N + k] = hv;
-      hsum += hv;
+      const double h = (double)hv[i];
+      b.h[(size_t)i * N + k] = h;
+      hsum += h;
     }
   }
   const unsigned on = nbase(g.sg, x, y);
@@ -285,24 +295,37 @@ __global__ __launch_bounds__(kB) void k_adj_b1(AGrid g, ACon c, ABuf b, const do
   const double dqx = b.dQ[k], dqy = b.dQ[N + k], D = b.D[k];
   double lP = 0, lrho = 0, lux = 0, luy = 0, lFx = 0, lFy = 0, lgx = 0, lgy = 0, lphi = 0, lmu = 0, lD = 0;
   double ldqx = 0, ldqy = 0, lom = 0, gM = 0;
+  // transpose of streaming: the post-collision value of direction i at x
+  // became population i at x + c_i, or population opp(i) at x at a wall.
+  // All adjoint values and populations are loaded before the per-direction
+  // stores below (separate buffers), so the loads are in flight together.
+  bool hit_[9];
+  double cuw_[9], lfp_[9], lhp_[9], fi_[9];
+#pragma unroll
   for (int i = 0; i < 9; ++i) {
-    // transpose of streaming: the post-collision value of direction i at x
-    // became population i at x + c_i, or population opp(i) at x at a wall
     int tx = x + cx(i), ty = y + cy(i);
     bool hit = false;
     double cuw = 0;
-    if (tx < 0 || tx >= g.nx) { if (g.wx) { hit = true; cuw = cy(i) * (tx < 0 ? c.uw_lo : c.uw_hi); } else tx = (tx + g.nx) % g.nx; }
-    if (ty < 0 || ty >= g.ny) { if (g.wy) { hit = true; cuw = cx(i) * (ty < 0 ? c.uw_lo : c.uw_hi); } else ty = (ty + g.ny) % g.ny; }
+    if (tx < 0 || tx >= g.nx) { if (g.wx) { hit = true; cuw = cy(i) * (tx < 0 ? c.uw_lo : c.uw_hi); } else tx = tx < 0 ? tx + g.nx : tx - g.nx; }
+    if (ty < 0 || ty >= g.ny) { if (g.wy) { hit = true; cuw = cx(i) * (ty < 0 ? c.uw_lo : c.uw_hi); } else ty = ty < 0 ? ty + g.ny : ty - g.ny; }
     const int slot = hit ? opp(i) : i;
     const int tgt = hit ? k : i0(g, tx, ty);
-    const double lfp = lam[(size_t)slot * N + tgt];
-    const double lhp = lam[(size_t)(9 + slot) * N + tgt];
+    hit_[i] = hit;
+    cuw_[i] = cuw;
+    lfp_[i] = lam[(size_t)slot * N + tgt];
+    lhp_[i] = lam[(size_t)(9 + slot) * N + tgt];
+    fi_[i] = b.f[(size_t)i * N + k];
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const bool hit = hit_[i];
+    const double cuw = cuw_[i], lfp = lfp_[i], lhp = lhp_[i];
     if (hit) {   // f_opp = f_i^+ - 2 w_i rho c_i.u_w ; h_opp = h_i^+ - 6 w_i phi c_i.u_w
       lrho += -2.0 * wtd(i) * cuw * lfp;
       lphi += -6.0 * wtd(i) * cuw * lhp;
     }
     // flow collision f^+ = (1 - om) f + om feq + cf F_i
-    const double fi = b.f[(size_t)i * N + k];
+    const double fi = fi_[i];
     const double cu = cx(i) * ux + cy(i) * uy;
     const double si = 3.0 * cu + 4.5 * cu * cu - 1.5 * usq;
     const double feq = wtd(i) * (P + CS2 * rho * si);
