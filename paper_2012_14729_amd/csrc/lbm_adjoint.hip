@@ -396,9 +396,11 @@ __global__ __launch_bounds__(kB) void k_adj_b2(AGrid g, ABuf b) {
   const int ex = k % (g.nx + 2) - 1, ey = k / (g.nx + 2) - 1;
   double lqx = 0, lqy = 0;
   for (int i = 1; i < 9; ++i) {   // D(x) = 3 sum_i w_i c_i . Q1(x + c_i)
+    // out-of-range neighbours load node 0 and contribute zero (all loads in flight together)
     const int x = ex - cx(i), y = ey - cy(i);
-    if (x < 0 || x >= g.nx || y < 0 || y >= g.ny) continue;
-    const double ld = 3.0 * wtd(i) * b.lD[i0(g, x, y)];
+    const bool ok = x >= 0 && x < g.nx && y >= 0 && y < g.ny;
+    const double v = b.lD[ok ? i0(g, x, y) : 0];
+    const double ld = 3.0 * wtd(i) * (ok ? v : 0.0);
     lqx += cx(i) * ld;
     lqy += cy(i) * ld;
   }
@@ -573,12 +575,13 @@ __global__ __launch_bounds__(kB) void k_adj_b6(AGrid g, ABuf b) {
   const int zx = k % (g.nx + 4) - 2, zy = k / (g.nx + 4) - 2;
   const bool in1 = zx >= -1 && zx <= g.nx && zy >= -1 && zy <= g.ny;
   double acc = 0;
-  for (int i = 1; i < 9; ++i) {
+  for (int i = 1; i < 9; ++i) {   // out-of-range: load position 0, contribute zero
     const int ex = zx - cx(i), ey = zy - cy(i);
-    if (ex < -1 || ex > g.nx || ey < -1 || ey > g.ny) continue;
-    const int e = i1(g, ex, ey);
-    acc += 3.0 * wtd(i) * (cx(i) * b.lG1[e] + cy(i) * b.lG1[ne + e]);
-    acc += 6.0 * wtd(i) * b.lL1[e];
+    const bool ok = ex >= -1 && ex <= g.nx && ey >= -1 && ey <= g.ny;
+    const int e = ok ? i1(g, ex, ey) : 0;
+    const double gx = b.lG1[e], gy = b.lG1[ne + e], l = b.lL1[e];
+    acc += 3.0 * wtd(i) * (cx(i) * (ok ? gx : 0.0) + cy(i) * (ok ? gy : 0.0));
+    acc += 6.0 * wtd(i) * (ok ? l : 0.0);
   }
   if (in1) {
     const int e = i1(g, zx, zy);
