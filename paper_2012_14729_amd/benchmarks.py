@@ -127,6 +127,8 @@ def capillary_wave(form: str, H: int = 80, rho_ratio: float = 1.0, h0: float = 0
     normalised amplitude history h(t)/h0 against theory (Eqs. 44-46) and the
     time-averaged error E2 (Eq. 47).  h0 (a fraction of H) is not given in
     the paper: 0.01 H by default."""
+    if not (0.0 < h0 < 0.5):
+        raise ValueError("h0 (the initial amplitude as a fraction of H) must lie in (0, 0.5)")
     nx, ny = H, 3 * H
     Re, We = 50.0, 1.0
     nu = U_c * H / Re

@@ -39,3 +39,11 @@ def test_viscosity_damps_and_the_error_norm_vanishes_on_the_exact_curve():
     assert np.abs(h[-200:]).max() < 0.1 < np.abs(h[:200]).max()
     assert T.capillary_error(t, h, nu, K, 1.0, 1.0, SIG) < 1e-12
     assert abs(T.capillary_error(t, h + 0.01, nu, K, 1.0, 1.0, SIG) - 0.01) < 1e-6
+
+
+@pytest.mark.parametrize("h0", [0.0, -0.01, 0.5])
+def test_capillary_benchmark_rejects_amplitudes_outside_the_box(h0):
+    """The benchmark validates its amplitude before touching the GPU."""
+    from paper_2012_14729_amd.benchmarks import capillary_wave
+    with pytest.raises(ValueError):
+        capillary_wave("stf2", H=16, h0=h0)
