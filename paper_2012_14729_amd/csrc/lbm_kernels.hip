@@ -527,11 +527,11 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
   const unsigned on = nbase(g, x, y);   // general path: plane 0 of this node (valid nodes)
 
   // This node's flow populations are pulled after the ring velocities (the
-  // ring threads would otherwise hold both sets of registers at once).  On
-  // interior tiles the ring threads request their ring node's populations
-  // right after staging the order parameter, so those loads are in flight
-  // through the first barrier and the stencil stage: nothing waits for
-  // them before the ring's velocities.
+  // ring threads would otherwise hold both sets of registers at once).  The
+  // ring threads request their ring node's populations right after staging
+  // the order parameter, so those loads are in flight through the first
+  // barrier and the stencil stage: nothing waits for them before the ring's
+  // velocities.
   float ft[9], ps[9], h[9];
   float j0 = 0.f, j1 = 0.f;
   // Only ring threads define these.  The others start from a kernel
@@ -594,7 +594,7 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
   // the CSF forms, and the stress forms need those registers for the ring).
   constexpr bool kEarlyOwn = FAST && FORM >= 2 && FORM <= 5;
   // The same forms also request their h and (phi u) pulls before the last
-  // barrier (measured: CPF and PF -1 to -2 us; the stress and CSF forms
+  // barrier (measured: CPF and PF -1 to -6 us; the stress and CSF forms
   // would spill or slow down).
   constexpr bool kEarlyH = kEarlyOwn;
   unsigned v3[3] = {0u, 0u, 0u};
