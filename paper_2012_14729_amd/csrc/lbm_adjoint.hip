@@ -186,6 +186,12 @@ __global__ __launch_bounds__(kB) void k_adj_fc(AGrid g, ACon c, ABuf b) {
   const int ne = (g.nx + 2) * (g.ny + 2);
   const int e = i1(g, x, y);
   const double phi = b.phi[k], gx = b.G1[e], gy = b.G1[ne + e], l = b.L1[e], mu = b.mu1[e];
+  // the populations are read before anything is stored (stores and loads
+  // share one in-order counter, and the compiler cannot move a load above a
+  // store to a buffer it cannot prove disjoint)
+  double fv[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) fv[i] = b.f[(size_t)i * N + k];
   double fx = 0, fy = 0, dn = 0;
   if (c.form <= 1) {
     for (int i = 1; i < 9; ++i) {
@@ -231,7 +237,7 @@ __global__ __launch_bounds__(kB) void k_adj_fc(AGrid g, ACon c, ABuf b) {
   b.rho[k] = rho; b.muv[k] = muv; b.tauf[k] = 0.5 + muv / (CS2 * rho);
   double jx = 0, jy = 0, S = 0;
   for (int i = 0; i < 9; ++i) {
-    const double fi = b.f[(size_t)i * N + k];
+    const double fi = fv[i];
     jx += cx(i) * fi; jy += cy(i) * fi; S += fi;
   }
   const double ux = (jx + 0.5 * CS2 * Fx) / (CS2 * rho), uy = (jy + 0.5 * CS2 * Fy) / (CS2 * rho);
@@ -417,55 +423,70 @@ __global__ __launch_bounds__(kB) void k_adj_b3(AGrid g, ACon c, ABuf b) {
   const int k = blockIdx.x * kB + threadIdx.x;
   if (k >= N) return;
   const int x = k % g.nx, y = k / g.nx;
+  const int e = i1(g, x, y);
+  // Every value this thread reads is loaded before its first store: stores
+  // and loads share one in-order counter, and the compiler cannot move a
+  // load above a store to a buffer it cannot prove disjoint.
   double lux = b.lu[k], luy = b.lu[N + k];
   int px[3], rx[3], py[3], ry[3];
   const int mx = preimages(x, g.nx, g.wx, 1, px, rx), my = preimages(y, g.ny, g.wy, 1, py, ry);
   for (int a = 0; a < mx; ++a)
     for (int bb = 0; bb < my; ++bb) {
-      const int e = i1(g, px[a], py[bb]);
+      const int q = i1(g, px[a], py[bb]);
       const double sg = ((rx[a] + ry[bb]) & 1) ? -1.0 : 1.0;
-      lux += sg * b.lue1[e];
-      luy += sg * b.lue1[ne + e];
+      lux += sg * b.lue1[q];
+      luy += sg * b.lue1[ne + q];
     }
   const double rho = b.rho[k], ux = b.u[k], uy = b.u[N + k];
-  const double ljx = lux / (CS2 * rho), ljy = luy / (CS2 * rho);
-  double lFx = b.lF[k] + 0.5 * lux / rho, lFy = b.lF[N + k] + 0.5 * luy / rho;
-  double lrho = b.lrho[k] - (ux * lux + uy * luy) / rho;
-  const double lS = b.lP[k];
-  // all nine planes read before any is written (the compiler cannot tell
-  // the planes apart, so interleaved updates would wait one at a time)
+  const double lF0x = b.lF[k], lF0y = b.lF[N + k], lrho0 = b.lrho[k], lS = b.lP[k], lphi0 = b.lphi[k];
   double lfv[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) lfv[i] = b.lf[(size_t)i * N + k];
+  const bool cpf1_pf2 = c.form == 2 || c.form == 5;
+  double fv[9];
+  if (cpf1_pf2) {
+    const double* fld = c.form == 2 ? b.mu1 : b.L1;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) fv[i] = fld[i1(g, x + cx(i), y + cy(i))];
+  }
+  const bool sig_f = !(c.form == 2 || c.form == 3);
+  const double fsx = sig_f ? b.Fsf[k] : 0.0, fsy = sig_f ? b.Fsf[N + k] : 0.0;
+  const double gsig0 = sig_f ? b.gsig[e] : 0.0;
+  const double lgr0x = b.lgr[k], lgr0y = b.lgr[N + k];
+  double g1x = 0.0, g1y = 0.0, n1x = 0.0, n1y = 0.0;
+  if (c.form >= 6) {
+    g1x = b.G1[e]; g1y = b.G1[ne + e];
+    if (c.form == 6) { n1x = b.n1[e]; n1y = b.n1[ne + e]; }
+  }
+
+  const double ljx = lux / (CS2 * rho), ljy = luy / (CS2 * rho);
+  double lFx = lF0x + 0.5 * lux / rho, lFy = lF0y + 0.5 * luy / rho;
+  double lrho = lrho0 - (ux * lux + uy * luy) / rho;
 #pragma unroll
   for (int i = 0; i < 9; ++i) b.lf[(size_t)i * N + k] = lfv[i] + (cx(i) * ljx + cy(i) * ljy + lS);
   lrho += c.gx * lFx + c.gy * lFy;
   b.lF[k] = lFx; b.lF[N + k] = lFy;   // now the adjoint of F_sf
-  double lphi = b.lphi[k] + c.drho_h * lrho;
-  const double phi = b.phi[k];
+  double lphi = lphi0 + c.drho_h * lrho;
   // point-wise parts of the force transposes that touch phi (CPF-1, PF-2)
-  if (c.form == 2 || c.form == 5) {
-    const double* fld = c.form == 2 ? b.mu1 : b.L1;
+  if (cpf1_pf2) {
     double ax = 0, ay = 0;
+#pragma unroll
     for (int i = 1; i < 9; ++i) {
-      const double v = fld[i1(g, x + cx(i), y + cy(i))];
-      ax += wtd(i) * cx(i) * v;
-      ay += wtd(i) * cy(i) * v;
+      ax += wtd(i) * cx(i) * fv[i];
+      ay += wtd(i) * cy(i) * fv[i];
     }
     const double s = c.form == 2 ? -3.0 : 3.0 * c.kappa;
     lphi += s * (ax * lFx + ay * lFy);
   }
   b.lphi[k] = lphi;
   // sigma enters F_sf linearly for every form except through mu (CPF forms)
-  if (!(c.form == 2 || c.form == 3)) b.gsig[i1(g, x, y)] += (b.Fsf[k] * lFx + b.Fsf[N + k] * lFy) / c.sigma;
+  if (sig_f) b.gsig[e] = gsig0 + (fsx * lFx + fsy * lFy) / c.sigma;
   // grad rho = (rho1 - rho2)/2 G  -> lambda_G contribution kept in lgr
-  b.lgr[k] *= c.drho_h;
-  b.lgr[N + k] *= c.drho_h;
+  b.lgr[k] = lgr0x * c.drho_h;
+  b.lgr[N + k] = lgr0y * c.drho_h;
   if (c.form >= 6) {   // adjoint of div n at the node (stored in lD, free after b2)
-    const int e = i1(g, x, y);
-    const double gx = b.G1[e], gy = b.G1[ne + e];
-    b.lD[k] = c.form == 6 ? -c.kappa * (gx * gx + gy * gy) * (b.n1[e] * lFx + b.n1[ne + e] * lFy)
-                          : -0.5 * c.sigma * (gx * lFx + gy * lFy);
+    b.lD[k] = c.form == 6 ? -c.kappa * (g1x * g1x + g1y * g1y) * (n1x * lFx + n1y * lFy)
+                          : -0.5 * c.sigma * (g1x * lFx + g1y * lFy);
   }
 }
 
