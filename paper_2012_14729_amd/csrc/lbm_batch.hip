@@ -150,16 +150,17 @@ int launch_pair_steps(lbm_batch* b, const BatchCfg& c, int nsteps, int parity0, 
       for (int f = 0; f < LBM_NUM_FORMS; ++f) {
         const int t0 = b->form_beg[f], t1 = b->form_beg[f + 1];
         if (t1 > t0)
-          BHIP(launch_batch_fused(b->d_inst(), b->d_tiles(), t0, t1, f, c.fast, par, grid_for(b, c, t1 - t0), st));
+          BHIP(launch_batch_fused(b->d_inst(), b->d_tiles(), b->ws, t0, t1, f, c.fast, par, grid_for(b, c, t1 - t0),
+                                  st));
       }
     } else {
-      BHIP(launch_batch_fused(b->d_inst(), b->d_tiles(), 0, b->L.ntiles, -1, c.fast, par, grid_for(b, c, b->L.ntiles),
-                              st));
+      BHIP(launch_batch_fused(b->d_inst(), b->d_tiles(), b->ws, 0, b->L.ntiles, -1, c.fast, par,
+                              grid_for(b, c, b->L.ntiles), st));
     }
     // The order-parameter pass holds few registers: one workgroup per tile
     // keeps far more of them resident than the fused kernel's persistent grid.
-    BHIP(launch_batch_phi(b->d_inst(), b->d_tiles(), b->L.ntiles, par, grid_for(b, BatchCfg{c.split, c.fast, 0, 0.0},
-                                                                                 b->L.ntiles), st));
+    BHIP(launch_batch_phi(b->d_inst(), b->d_tiles(), b->ws, b->L.ntiles, par,
+                          grid_for(b, BatchCfg{c.split, c.fast, 0, 0.0}, b->L.ntiles), st));
     par = 1 - par;
   }
   return LBM_OK;
@@ -376,6 +377,10 @@ int lbm_batch_create(lbm_batch** out, const lbm_params* params, const int32_t* f
       a.g = I.g;
       a.c = c;
     }
+    b->host[k].off_s[0] = (long long)I.s[0];
+    b->host[k].off_s[1] = (long long)I.s[1];
+    b->host[k].off_phi = (long long)I.phi;
+    b->host[k].off_status = (long long)((char*)(b->d_status() + k) - ws);
     b->host[k].form = forms[k];
   }
   // tile list: by force form, then instance, then row-major tiles

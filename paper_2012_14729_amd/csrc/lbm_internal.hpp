@@ -93,8 +93,12 @@ struct MomentArgs {
 
 // One instance of a batch: its step arguments for both ping-pong parities
 // (a[p] reads population buffer p and writes buffer 1 - p) and its force form.
+// The kernels rebuild the pointers from byte offsets into the batch workspace
+// (a kernel argument), so that they are known to address global memory.
 struct BatchInst {
   StepArgs a[2];
+  long long off_s[2];   // population buffers 0 and 1
+  long long off_phi, off_status;
   int form;
   int pad[3];
 };
@@ -141,9 +145,9 @@ hipError_t launch_copies(const void* const* src, void* const* dst, const size_t*
                          size_t zero_bytes, hipStream_t s);
 // persistent batched step kernels over a tile list (periodic instances); form < 0:
 // one kernel for every form, else the tiles [t0, t1) all have that form
-hipError_t launch_batch_fused(const BatchInst* inst, const TileRef* tiles, int t0, int t1, int form, int fast,
-                              int parity, int nblocks, hipStream_t s);
-hipError_t launch_batch_phi(const BatchInst* inst, const TileRef* tiles, int ntiles, int parity, int nblocks,
+hipError_t launch_batch_fused(const BatchInst* inst, const TileRef* tiles, char* ws, int t0, int t1, int form,
+                              int fast, int parity, int nblocks, hipStream_t s);
+hipError_t launch_batch_phi(const BatchInst* inst, const TileRef* tiles, char* ws, int ntiles, int parity, int nblocks,
                             hipStream_t s);
 int fused_blocks_per_cu();
 

@@ -873,11 +873,24 @@ __device__ __forceinline__ void batch_tile(Lds& s, const StepArgs& a, int tx, in
   else tile_impl<FORM, false, 0, false, true>(s, a, MomentArgs{}, tx, ty);
 }
 
+// Step arguments of a batch instance with its pointers rebuilt from the
+// workspace base, a kernel argument: pointers read from the descriptor would
+// be generic, and every access through them a flat one (which also counts
+// against the LDS wait counter).
+__device__ __forceinline__ StepArgs batch_args(const BatchInst& bi, int parity, char* ws) {
+  StepArgs a = bi.a[parity];
+  a.sin = (const float*)(ws + bi.off_s[parity]);
+  a.sout = (float*)(ws + bi.off_s[1 - parity]);
+  a.phi = (const double*)(ws + bi.off_phi);
+  a.status = (int*)(ws + bi.off_status);
+  return a;
+}
+
 // FORM >= 0: every tile of [t0, t1) has that force form (the tile list is
 // sorted by form); FORM < 0: any form, dispatched per tile.
 template <int FORM, bool FAST_OK>
 __global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_fused(
-    const BatchInst* __restrict__ inst, const TileRef* __restrict__ tiles, int t0, int t1, int parity) {
+    const BatchInst* __restrict__ inst, const TileRef* __restrict__ tiles, char* ws, int t0, int t1, int parity) {
   __shared__ Lds s;
   int first, end, stride;
   band(t0, t1, first, end, stride);
@@ -885,7 +898,7 @@ __global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(4
     const TileRef tr = tiles[t];
     const BatchInst& bi = inst[tr.inst];
     __syncthreads();   // the previous tile is done with the LDS
-    const StepArgs& a = bi.a[parity];
+    const StepArgs a = batch_args(bi, parity, ws);
     if constexpr (FORM >= 0) {
       batch_tile<FORM, FAST_OK>(s, a, tr.tx, tr.ty);
     } else {
@@ -904,12 +917,13 @@ __global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(4
 }
 
 __global__ __launch_bounds__(kFusedThreads) void k_batch_phi(const BatchInst* __restrict__ inst,
-                                                             const TileRef* __restrict__ tiles, int ntiles, int parity) {
+                                                             const TileRef* __restrict__ tiles, char* ws, int ntiles,
+                                                             int parity) {
   int first, end, stride;
   band(0, ntiles, first, end, stride);
   for (int t = first; t < end; t += stride) {
     const TileRef tr = tiles[t];
-    const StepArgs& a = inst[tr.inst].a[parity];
+    const StepArgs a = batch_args(inst[tr.inst], parity, ws);
     phi_tile<0>(a.sout, const_cast<double*>(a.phi), a.g, tr.tx, tr.ty);
   }
 }
@@ -1150,32 +1164,34 @@ hipError_t launch_fill_int(int* p, int value, int n, hipStream_t s) {
 namespace pflbm {
 
 template <int FORM>
-void launch_batch_form(bool fast, dim3 grid, hipStream_t s, const BatchInst* inst, const TileRef* tiles, int t0,
-                       int t1, int parity) {
-  if (fast) hipLaunchKernelGGL((k_batch_fused<FORM, true>), grid, dim3(kFusedThreads), 0, s, inst, tiles, t0, t1, parity);
-  else hipLaunchKernelGGL((k_batch_fused<FORM, false>), grid, dim3(kFusedThreads), 0, s, inst, tiles, t0, t1, parity);
+void launch_batch_form(bool fast, dim3 grid, hipStream_t s, const BatchInst* inst, const TileRef* tiles, char* ws,
+                       int t0, int t1, int parity) {
+  if (fast)
+    hipLaunchKernelGGL((k_batch_fused<FORM, true>), grid, dim3(kFusedThreads), 0, s, inst, tiles, ws, t0, t1, parity);
+  else
+    hipLaunchKernelGGL((k_batch_fused<FORM, false>), grid, dim3(kFusedThreads), 0, s, inst, tiles, ws, t0, t1, parity);
 }
 
-hipError_t launch_batch_fused(const BatchInst* inst, const TileRef* tiles, int t0, int t1, int form, int fast,
-                              int parity, int nblocks, hipStream_t s) {
+hipError_t launch_batch_fused(const BatchInst* inst, const TileRef* tiles, char* ws, int t0, int t1, int form,
+                              int fast, int parity, int nblocks, hipStream_t s) {
   const dim3 grid(nblocks);
   switch (form) {
-    case 0: launch_batch_form<0>(fast, grid, s, inst, tiles, t0, t1, parity); break;
-    case 1: launch_batch_form<1>(fast, grid, s, inst, tiles, t0, t1, parity); break;
-    case 2: launch_batch_form<2>(fast, grid, s, inst, tiles, t0, t1, parity); break;
-    case 3: launch_batch_form<3>(fast, grid, s, inst, tiles, t0, t1, parity); break;
-    case 4: launch_batch_form<4>(fast, grid, s, inst, tiles, t0, t1, parity); break;
-    case 5: launch_batch_form<5>(fast, grid, s, inst, tiles, t0, t1, parity); break;
-    case 6: launch_batch_form<6>(fast, grid, s, inst, tiles, t0, t1, parity); break;
-    case 7: launch_batch_form<7>(fast, grid, s, inst, tiles, t0, t1, parity); break;
-    default: launch_batch_form<-1>(fast, grid, s, inst, tiles, t0, t1, parity); break;
+    case 0: launch_batch_form<0>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    case 1: launch_batch_form<1>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    case 2: launch_batch_form<2>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    case 3: launch_batch_form<3>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    case 4: launch_batch_form<4>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    case 5: launch_batch_form<5>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    case 6: launch_batch_form<6>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    case 7: launch_batch_form<7>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    default: launch_batch_form<-1>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_batch_phi(const BatchInst* inst, const TileRef* tiles, int ntiles, int parity, int nblocks,
+hipError_t launch_batch_phi(const BatchInst* inst, const TileRef* tiles, char* ws, int ntiles, int parity, int nblocks,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_phi, dim3(nblocks), dim3(kFusedThreads), 0, s, inst, tiles, ntiles, parity);
+  hipLaunchKernelGGL(k_batch_phi, dim3(nblocks), dim3(kFusedThreads), 0, s, inst, tiles, ws, ntiles, parity);
   return hipGetLastError();
 }
 
