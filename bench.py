@@ -201,8 +201,11 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (multi-GPU sharding is a "
-              f"design note, not part of this build)", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported: the multi-GPU slab "
+              f"decomposition is not implemented", file=sys.stderr)
+        sys.exit(2)
+    if args.steps % 8 or args.steps < 8:
+        print("bench.py: --steps must be a positive multiple of 8 (one run per force form)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -219,9 +222,6 @@ def main():
     sims = [P.Simulation(p.as_dict(), phi0, device=dev) for _ in FORMS]
     cells = p.nx * p.ny
 
-    if args.steps % 8 or args.steps < 8:
-        print("bench.py: --steps must be a positive multiple of 8 (one run per force form)", file=sys.stderr)
-        sys.exit(2)
     for k, (s, f) in enumerate(zip(sims, FORMS)):
         s.step(max(1, args.warmup // 8), f)
     torch.cuda.synchronize()
