@@ -1041,22 +1041,22 @@ struct CopyJob {
   const unsigned* src[3];
   unsigned* dst[3];
   long long n[3];        // words
+  long long nv[3];       // leading 16-byte groups (0 unless both ends are 16-byte aligned)
   unsigned* zero;        // words set to 0
   long long nzero;
 };
 
+// Each job: its 16-byte groups first, then the words past the last group.
 __global__ __launch_bounds__(256) void k_copy_jobs(CopyJob j) {
-  const long long tot = j.n[0] + j.n[1] + j.n[2] + j.nzero;
-  for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < tot; k += (long long)gridDim.x * 256) {
-    long long r = k;
-    if (r < j.n[0]) { j.dst[0][r] = j.src[0][r]; continue; }
-    r -= j.n[0];
-    if (r < j.n[1]) { j.dst[1][r] = j.src[1][r]; continue; }
-    r -= j.n[1];
-    if (r < j.n[2]) { j.dst[2][r] = j.src[2][r]; continue; }
-    r -= j.n[2];
-    j.zero[r] = 0u;
+  const long long stride = (long long)gridDim.x * 256, t0 = (long long)blockIdx.x * 256 + threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const uint4* s4 = reinterpret_cast<const uint4*>(j.src[q]);
+    uint4* d4 = reinterpret_cast<uint4*>(j.dst[q]);
+    for (long long k = t0; k < j.nv[q]; k += stride) d4[k] = s4[k];
+    for (long long k = 4 * j.nv[q] + t0; k < j.n[q]; k += stride) j.dst[q][k] = j.src[q][k];
   }
+  for (long long k = t0; k < j.nzero; k += stride) j.zero[k] = 0u;
 }
 
 __global__ void k_fill_int(int* p, int v, int n) {
@@ -1143,7 +1143,9 @@ hipError_t launch_copies(const void* const* src, void* const* dst, const size_t*
     j.src[k] = k < njobs ? (const unsigned*)src[k] : nullptr;
     j.dst[k] = k < njobs ? (unsigned*)dst[k] : nullptr;
     j.n[k] = k < njobs ? (long long)(bytes[k] / 4) : 0;
-    tot += j.n[k];
+    const bool al = (((uintptr_t)j.src[k] | (uintptr_t)j.dst[k]) & 15) == 0;
+    j.nv[k] = al ? j.n[k] / 4 : 0;
+    tot += j.n[k] - 3 * j.nv[k];   // work items: one per group, one per leftover word
   }
   j.zero = (unsigned*)zero;
   j.nzero = zero ? (long long)(zero_bytes / 4) : 0;
