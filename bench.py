@@ -6,13 +6,16 @@ Workload: the stationary droplet on a 2048x2048 periodic lattice (R = 256,
 W = 5, density ratio 1000, dynamic viscosity ratio 100, sigma = 1e-3), one
 run per interfacial-force form; a "step" is one time step (fused
 collide-stream kernel + order-parameter kernel) of one of the eight
-simulations.  The timed K steps are eight consecutive runs of K/8 steps, one
-per form, back to back.  All state is resident in HBM before the timed
-region.
+simulations.  The timed K steps (any K >= 1) are consecutive runs, one per
+form in the paper's order, of K // 8 steps each plus one more step for each
+of the first K % 8 forms; a form with no step is skipped.  All state is
+resident in HBM before the timed region.
 
 Prints one JSON line with MLUPS, the roofline of the fused kernel (HIP
 events recorded on the launch stream during the timed region), the oracle
-timed on the host cores, per-form MLUPS and the batched/adjoint figures.
+timed on the host cores (all of this process's cores and one core),
+per-form MLUPS, the spurious-current maximum after 10000 steps per form and
+the batched/adjoint figures.
 """
 from __future__ import annotations
 
@@ -28,10 +31,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per node and launch (FP32 populations, FP64 phi):
-#   fused: read 9 f + P + 8 h (pulled) + 2 J + phi(8 B); write 9 f + P + 8 h + d0 + 2 J
-#   phi  : read d0 + 8 h (pulled) + phi(8 B); write phi(8 B)
+# Algorithmic bytes per node of the collide-stream step (FP32): read and write
+# the 9 f and 9 h populations (144 B), read and write the (phi u) history
+# (16 B), read phi (4 B) = 164 B.
+BYTES_FUSED_ALG = 9 * 4 * 2 + 9 * 4 * 2 + 2 * 4 * 2 + 4
+# What this design's fused kernel moves per node (FP32 populations, FP32
+# pressure plane, FP64 phi): read 9 f + P + 8 h (pulled) + 2 J + phi (8 B);
+# write 9 f + P + 8 h + d0 + 2 J.
 BYTES_FUSED = 9 * 4 + 4 + 8 * 4 + 2 * 4 + 8 + 9 * 4 + 4 + 9 * 4 + 2 * 4
+#   order-parameter kernel: read d0 + 8 h (pulled) + phi (8 B); write phi (8 B)
 BYTES_PHI = 4 + 8 * 4 + 8 + 8
 FORMS = ("stf1", "stf2", "cpf1", "cpf2", "pf1", "pf2", "csf1", "csf2")
 TIMING_PERIOD = 8   # kernel durations: HIP events on one step in eight of the timed region
@@ -55,9 +63,25 @@ def measured_traffic():
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(budget_s=20.0):
-    """The oracle (FP64, torch CPU) on the same 2048x2048 droplet: one warm-up
-    step, then steps until about budget_s seconds have passed."""
+def _host_cpu():
+    """CPU model and logical-CPU count of the host, read from /proc/cpuinfo."""
+    model, n = None, 0
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("processor"):
+                n += 1
+            elif model is None and line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return model, n
+
+
+def cpu_baseline(budget_all_s=15.0, budget_one_s=12.0):
+    """The oracle (FP64, torch CPU) on the same 2048x2048 droplet, timed
+    twice: with every core this process may use (torch intra-op threads =
+    its CPU affinity, capped by OMP_NUM_THREADS when set), then on one core.
+    Each leg steps (forms round-robin) until about its budget has passed."""
     import numpy as np
     import torch
 
@@ -66,19 +90,39 @@ def cpu_baseline(budget_s=20.0):
 
     p, phi0, _, _ = WL.config_droplet_large(2048)
     op = R.Params(**{k: (None if k == "rho0" else v) for k, v in p.as_dict().items()})
-    st = R.init(op, torch.tensor(np.asarray(phi0, np.float32), dtype=torch.float64))
-    st = R.step(st, "stf1", op)
-    n, t0 = 0, time.perf_counter()
-    while True:
-        st = R.step(st, FORMS[n % 8], op)
-        n += 1
-        el = time.perf_counter() - t0
-        if el > budget_s or n >= 64:
-            break
     cells = p.nx * p.ny
-    return {"value": round(cells * n / el / 1e6, 3), "unit": "MLUPS", "cores": torch.get_num_threads(),
-            "kind": "oracle",
-            "sample": f"{n} time steps of the 2048x2048 droplet (forms round-robin, FP64 torch CPU) after 1 warm-up step, {el:.1f} s"}
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    threads = min(avail, int(omp)) if omp.isdigit() and int(omp) > 0 else avail
+    prev = torch.get_num_threads()
+
+    def leg(nthreads, budget, st):
+        torch.set_num_threads(nthreads)
+        n, t0 = 0, time.perf_counter()
+        while True:
+            st = R.step(st, FORMS[n % 8], op)
+            n += 1
+            el = time.perf_counter() - t0
+            if el > budget or n >= 64:
+                return st, n, el
+
+    try:
+        torch.set_num_threads(threads)
+        st = R.init(op, torch.tensor(np.asarray(phi0, np.float32), dtype=torch.float64))
+        st = R.step(st, "stf1", op)   # warm-up
+        st, n_all, el_all = leg(threads, budget_all_s, st)
+        st, n_one, el_one = leg(1, budget_one_s, st)
+    finally:
+        torch.set_num_threads(prev)
+    model, logical = _host_cpu()
+    all_rate = cells * n_all / el_all / 1e6
+    one_rate = cells * n_one / el_one / 1e6
+    return {"value": round(all_rate, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{n_all} time steps of the 2048x2048 droplet (forms round-robin, FP64 torch CPU, "
+                      f"{threads} threads) after 1 warm-up step, {el_all:.1f} s",
+            "one_core": {"value": round(one_rate, 3), "unit": "MLUPS", "cores": 1,
+                         "sample": f"{n_one} further time steps on 1 thread, {el_one:.1f} s"},
+            "host": {"cpu_model": model, "logical_cpus_on_host": logical, "cpus_available_to_process": avail}}
 
 
 def bench_batched(steps, loop_steps):
@@ -188,25 +232,72 @@ def bench_adjoint(T):
             "loss": loss, "dL_dsigma": dsig, "dL_dM": dM, "max_abs_dL_dphi0": float(dphi0.abs().max())}
 
 
-def main():
+def split_steps(steps, nforms=len(FORMS)):
+    """Steps per force form: steps // nforms each, one more for each of the
+    first steps % nforms forms."""
+    base, extra = divmod(steps, nforms)
+    return [base + (1 if k < extra else 0) for k in range(nforms)]
+
+
+def parse_args(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1600)
     ap.add_argument("--warmup", type=int, default=80)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--size", type=int, default=2048)
+    ap.add_argument("--spurious-steps", type=int, default=10000,
+                    help="steps per form of the spurious-current leg (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=4000)
     ap.add_argument("--no-adjoint", action="store_true")
-    args = ap.parse_args()
+    ap.add_argument("--check-args", action="store_true", help="validate the arguments and exit (no GPU work)")
+    args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported: the multi-GPU slab "
               f"decomposition is not implemented", file=sys.stderr)
         sys.exit(2)
-    if args.steps % 8 or args.steps < 8:
-        print("bench.py: --steps must be a positive multiple of 8 (one run per force form)", file=sys.stderr)
+    if args.steps < 1:
+        print("bench.py: --steps must be a positive number of time steps", file=sys.stderr)
         sys.exit(2)
+    if args.warmup < 0 or args.spurious_steps < 0 or args.batch_steps < 1 or args.adjoint_steps < 1:
+        print("bench.py: --warmup and --spurious-steps must be >= 0, --batch-steps and --adjoint-steps >= 1",
+              file=sys.stderr)
+        sys.exit(2)
+    return args
+
+
+def spurious_leg(sims, nsteps, cells):
+    """Config-2 horizon: every form's droplet advanced to nsteps steps in
+    total; max|u| (the spurious current) then, and the rate of this leg."""
+    import torch
+
+    umax, done = {}, {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ran = 0
+    for f, s in sims.items():
+        todo = nsteps - s.step_count
+        if todo > 0:
+            s.step(todo, f)
+            ran += todo
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    for f, s in sims.items():
+        m = s.moments(f)
+        umax[f] = float(f"{float(torch.sqrt(m['ux'] ** 2 + m['uy'] ** 2).max()):.4g}")
+        done[f] = s.step_count
+    return {"steps_per_form": done, "max_abs_u": umax, "diverged": [f for f, s in sims.items() if s.status()],
+            "MLUPS": round(cells * ran / el / 1e6, 1) if ran else None}
+
+
+def main():
+    args = parse_args()
+    counts = split_steps(args.steps)
+    if args.check_args:
+        print(json.dumps({"steps_per_form": dict(zip(FORMS, counts))}))
+        return
 
     import numpy as np
     import torch
@@ -219,62 +310,67 @@ def main():
     p, phi0, _, _ = WL.config_droplet_large(args.size)
     phi0 = np.asarray(phi0, np.float32)
     print(f"[bench] building {len(FORMS)} simulations {p.nx}x{p.ny}", file=sys.stderr, flush=True)
-    sims = [P.Simulation(p.as_dict(), phi0, device=dev) for _ in FORMS]
+    sims = {f: P.Simulation(p.as_dict(), phi0, device=dev) for f in FORMS}
     cells = p.nx * p.ny
 
-    for k, (s, f) in enumerate(zip(sims, FORMS)):
-        s.step(max(1, args.warmup // 8), f)
+    wcounts = split_steps(args.warmup)
+    for (f, s), w in zip(sims.items(), wcounts):
+        s.step(max(1, w), f)
     torch.cuda.synchronize()
     print("[bench] warm-up done", file=sys.stderr, flush=True)
 
-    # the launch durations are sampled on one step in TIMING_PERIOD: events
-    # around every launch would add their own gaps to the timed region.  A
-    # period no longer than the steps each form runs times at least one of them.
-    per = args.steps // 8
-    for s in sims:
-        s.set_timing(True, period=min(TIMING_PERIOD, per))
+    # The launch durations are sampled on one step in `period`: events around
+    # every launch would add their own gaps to the timed region.  A period no
+    # longer than the shortest run times at least one step of every run.
+    timed = [(f, sims[f], n) for f, n in zip(FORMS, counts) if n > 0]
+    period = min([TIMING_PERIOD] + [n for _, _, n in timed])
+    for _, s, _ in timed:
+        s.set_timing(True, period=period)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for s, f in zip(sims, FORMS):
-        for _ in range(per):
+    for f, s, n in timed:
+        for _ in range(n):
             s.step(1, f)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    fused_ms = sum(s.kernel_time(0)[0] for s in sims)
-    fused_n = sum(s.kernel_time(0)[1] for s in sims)
-    phi_ms = sum(s.kernel_time(1)[0] for s in sims)
-    phi_n = sum(s.kernel_time(1)[1] for s in sims)
-    for s in sims:
+    fused_ms = sum(s.kernel_time(0)[0] for _, s, _ in timed)
+    fused_n = sum(s.kernel_time(0)[1] for _, s, _ in timed)
+    phi_ms = sum(s.kernel_time(1)[0] for _, s, _ in timed)
+    phi_n = sum(s.kernel_time(1)[1] for _, s, _ in timed)
+    for _, s, _ in timed:
         s.set_timing(False)
-    print(f"[bench] timed {args.steps} steps in {el:.3f} s", file=sys.stderr, flush=True)
-
-    diverged = [f for f, s in zip(FORMS, sims) if s.status()]
-    umax = {}
-    for f, s in zip(FORMS, sims):
-        m = s.moments(f)
-        umax[f] = float(torch.sqrt(m["ux"] ** 2 + m["uy"] ** 2).max())
+    print(f"[bench] timed {args.steps} steps in {el:.4f} s", file=sys.stderr, flush=True)
+    if fused_n == 0 or phi_n == 0:
+        raise RuntimeError("no kernel launch was timed")
+    diverged = [f for f, s, _ in timed if s.status()]
 
     # per-form rates, each form alone
     per_form = {}
     nper = max(8, args.steps // 16)
-    for f, s in zip(FORMS, sims):
+    for f, s in sims.items():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         s.step(nper, f)
         torch.cuda.synchronize()
         per_form[f] = round(cells * nper / (time.perf_counter() - t1) / 1e6, 1)
 
-    if fused_n == 0 or phi_n == 0:
-        raise RuntimeError("no kernel launch was timed")
     fused_avg_s = fused_ms / fused_n / 1e3
-    achieved = BYTES_FUSED * cells / fused_avg_s / 1e9
+    phi_avg_s = phi_ms / phi_n / 1e3
+    achieved = BYTES_FUSED_ALG * cells / fused_avg_s / 1e9
+    achieved_design = BYTES_FUSED * cells / fused_avg_s / 1e9
     traffic = measured_traffic()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_fused (collide-stream, all forms)", "bytes_per_node": BYTES_FUSED,
-                "avg_launch_us": round(fused_avg_s * 1e6, 2),
-                "phi_kernel": {"avg_launch_us": round(phi_ms / max(phi_n, 1) * 1e3, 2),
-                               "achieved_GBs": round(BYTES_PHI * cells / (phi_ms / max(phi_n, 1) / 1e3) / 1e9, 1)}}
+                "kernel": "k_fused (collide-stream, all forms)", "bytes_per_node": BYTES_FUSED_ALG,
+                "bytes_basis": "algorithmic: f and h read+write, (phi u) read+write, phi read (FP32)",
+                "nodes_per_launch": cells, "avg_launch_us": round(fused_avg_s * 1e6, 2),
+                "timed_launches": fused_n,
+                "design_basis": {"bytes_per_node": BYTES_FUSED, "achieved": round(achieved_design, 1),
+                                 "frac": round(achieved_design / HBM_PEAK_GBS, 4),
+                                 "note": "adds the FP32 pressure plane (read+write) and phi in FP64"},
+                "phi_kernel": {"avg_launch_us": round(phi_avg_s * 1e6, 2),
+                               "achieved_GBs": round(BYTES_PHI * cells / phi_avg_s / 1e9, 1),
+                               "bytes_per_node": BYTES_PHI}}
 
     value = cells * args.steps / el / 1e6
     out = {
@@ -283,23 +379,28 @@ def main():
         "ms_per_step": round(el / args.steps * 1e3, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"stationary droplet {p.nx}x{p.ny} periodic, R={p.nx // 8}, W=5, rho1/rho2=1000, "
-                               f"mu1/mu2=100, sigma=1e-3, one run per force form (8 runs of steps/8)",
-                   "precision": "FP32 storage of f, h, J, P; FP64 arithmetic (collision, stencils, forces) and FP64 phi",
+                               f"mu1/mu2=100, sigma=1e-3, one run per force form in the paper's order",
+                   "steps_per_form": dict(zip(FORMS, counts)),
+                   "precision": "FP64 arithmetic (collision, stencils, forces) and FP64 phi; "
+                                "FP32 storage of f, h, (phi u) and P",
+                   "storage_dtype": "fp32",
                    "step_bytes_per_node": BYTES_FUSED + BYTES_PHI,
                    "step_GBs": round((BYTES_FUSED + BYTES_PHI) * value * 1e6 / 1e9, 1)},
         "roofline": roofline,
         "per_form_MLUPS": per_form,
-        "spurious_umax": {k: float(f"{v:.4g}") for k, v in umax.items()},
         "diverged": diverged,
+        "spurious_current": None,
         "batched": None,
         "adjoint": None,
     }
-    value_per_form = value
+    if args.spurious_steps:
+        print(f"[bench] spurious-current leg: {args.spurious_steps} steps per form", file=sys.stderr, flush=True)
+        out["spurious_current"] = spurious_leg(sims, args.spurious_steps, cells)
+    del sims
+    torch.cuda.empty_cache()
     if not args.no_batch:
-        del sims
-        torch.cuda.empty_cache()
         out["batched"] = bench_batched(args.batch_steps, 20)
-        out["batched"]["vs_plain_step"] = round(out["batched"]["MLUPS"] / value_per_form, 3)
+        out["batched"]["vs_plain_step"] = round(out["batched"]["MLUPS"] / value, 3)
     if not args.no_adjoint:
         torch.cuda.empty_cache()
         out["adjoint"] = bench_adjoint(args.adjoint_steps)

@@ -1,7 +1,7 @@
 """Plain device-to-device copy of a known size, used to calibrate the HBM
 byte counters (FETCH_SIZE / WRITE_SIZE) read by rocprofv3.
 
-    python -m paper_2012_14729_amd.calib_copy [MiB] [repeats]
+    python calib_copy.py [MiB] [repeats]
 
 Each launch reads and writes MiB mebibytes once.
 """
