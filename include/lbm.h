@@ -102,7 +102,10 @@ int lbm_workspace_bytes(const lbm_params* p, size_t* bytes);
  * Tiles away from the domain edge use a faster addressing path with the
  * same arithmetic; the environment variable PFLBM_GENERAL_PATH=1, read here
  * and by lbm_batch_create, sends every tile through the general path
- * (diagnostics: both paths give bitwise identical states). */
+ * (diagnostics: both paths give bitwise identical states).  The step
+ * kernels work on 64x8-node tiles; PFLBM_TILE=1, 2 or 3 (read here) runs a
+ * periodic lattice's step on 32x16, 32x8 or 64x4 tiles instead (diagnostics
+ * and tuning: every shape gives bitwise identical states). */
 int lbm_init(lbm_sim** sim, const lbm_params* p, void* d_ws, size_t ws_bytes,
              const float* d_phi0, const float* d_ux0, const float* d_uy0, void* stream);
 

@@ -286,6 +286,63 @@ class Adjoint:
             pass
 
 
+class _Checkpointed:
+    """Forward pass of L = 1/2 sum (phi_T - target)^2 with a state checkpoint
+    every `every` steps, and the adjoint pass over it.
+
+    forward(): T steps from phi0, keeping (T / every) checkpoints; seeds
+    lambda_T and computes L (lbm_adjoint_seed_phi_misfit).
+    backward(): per segment in reverse, restore its checkpoint, recompute
+    the segment's per-step states into a pool of `every` state blobs
+    (allocated once and reused by every segment), run the adjoint steps
+    backwards over them; then the adjoint of the initialisation.  Memory:
+    (T / every + every) states."""
+
+    def __init__(self, params, form, T, phi0, target, ux0=None, uy0=None, every=None):
+        self.form, self.T = form, int(T)
+        self.every = max(1, int(math.ceil(math.sqrt(T)))) if every is None else int(every)
+        self.phi0, self.ux0, self.uy0, self.target = phi0, ux0, uy0, target
+        self.sim = Simulation(params, phi0, ux0, uy0, device=phi0.device)
+        self.adj = Adjoint(self.sim)
+        self.ckpt = []
+        self.lam = None
+        self.loss = None
+
+    def forward(self, keep_checkpoints=True):
+        sim = self.sim
+        if keep_checkpoints:
+            for t in range(self.T):
+                if t % self.every == 0:
+                    self.ckpt.append(sim.save())
+                sim.step(1, self.form)
+        else:
+            sim.step(self.T, self.form)
+        self.lam, self.loss = self.adj.seed_phi_misfit(self.target)
+        return self.loss
+
+    def backward(self):
+        if self.lam is None or (self.T > 0 and not self.ckpt):
+            raise RuntimeError("backward needs a forward pass that kept its checkpoints")
+        sim, adj, lam, every = self.sim, self.adj, self.lam, self.every
+        pool = [torch.empty_like(self.ckpt[0]) for _ in range(min(every, self.T))] if self.ckpt else []
+        L = lib()
+        for s in reversed(range(len(self.ckpt))):
+            t_lo, t_hi = s * every, min(self.T, (s + 1) * every)
+            sim.restore(self.ckpt[s])
+            for t in range(t_lo, t_hi):
+                check(L.lbm_save(sim._h, _ptr(pool[t - t_lo]), _stream(None)))
+                if t < t_hi - 1:
+                    sim.step(1, self.form)
+            for t in reversed(range(t_lo, t_hi)):
+                adj.step_blob(pool[t - t_lo], lam, self.form)
+            self.ckpt[s] = None   # this checkpoint is no longer needed
+        del pool
+        self.ckpt = []
+        dphi0 = adj.init(lam, self.phi0, self.ux0, self.uy0)
+        dsig, dM = adj.param_grads()
+        return dphi0, dsig, dM
+
+
 def adjoint_gradients(params, form, T, phi0, target, ux0=None, uy0=None, every=None, timings=None):
     """dL/dphi0, dL/dsigma, dL/dM of L = 1/2 sum (phi_T - target)^2.
 
@@ -295,61 +352,51 @@ def adjoint_gradients(params, form, T, phi0, target, ux0=None, uy0=None, every=N
     the adjoint steps run over it in reverse.  Memory: (T/every + every)
     states.  `timings`, if a dict, receives the forward and backward wall
     times (seconds, synchronised).  Returns (loss, dphi0 [float64], dsigma, dM)."""
-    if every is None:
-        every = max(1, int(math.ceil(math.sqrt(T))))
     sync = timings is not None
     if sync:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-    sim = Simulation(params, phi0, ux0, uy0, device=phi0.device)
-    adj = Adjoint(sim)
-    ckpt = []
-    for t in range(T):
-        if t % every == 0:
-            ckpt.append(sim.save())
-        sim.step(1, form)
-    lam, loss = adj.seed_phi_misfit(target)
+    run = _Checkpointed(params, form, T, phi0, target, ux0, uy0, every)
+    loss = run.forward()
+    nckpt = len(run.ckpt)
     if sync:
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-    for s in reversed(range(len(ckpt))):
-        t_lo, t_hi = s * every, min(T, (s + 1) * every)
-        sim.restore(ckpt[s])
-        states = []
-        for t in range(t_lo, t_hi):
-            states.append(sim.save())
-            if t < t_hi - 1:
-                sim.step(1, form)
-        for t in reversed(range(t_lo, t_hi)):
-            adj.step_blob(states[t - t_lo], lam, form)
-        del states
-    dphi0 = adj.init(lam, phi0, ux0, uy0)
-    dsig, dM = adj.param_grads()
+    dphi0, dsig, dM = run.backward()
     if sync:
         torch.cuda.synchronize()
         timings["forward_s"] = t1 - t0
         timings["backward_s"] = time.perf_counter() - t1
-        timings["checkpoints"] = len(ckpt)
-        timings["every"] = every
+        timings["checkpoints"] = nckpt
+        timings["every"] = run.every
     return loss, dphi0, dsig, dM
 
 
 class _Rollout(torch.autograd.Function):
+    """forward: the checkpointed forward pass only (L); backward: the adjoint
+    pass."""
+
     @staticmethod
     def forward(ctx, phi0, sigma, M, params, form, T, target, ux0, uy0, every):
         p = dict(params)
         p["sigma"] = float(sigma)
         p["M"] = float(M)
-        loss, dphi0, dsig, dM = adjoint_gradients(p, form, T, phi0.detach().float(), target, ux0, uy0, every)
-        ctx.save_for_backward(dphi0)
-        ctx.dsig, ctx.dM = dsig, dM
+        run = _Checkpointed(p, form, T, phi0.detach().float(), target, ux0, uy0, every)
+        loss = run.forward(keep_checkpoints=True)
+        ctx.run = run
         return torch.tensor(loss, dtype=torch.float64, device=phi0.device)
 
     @staticmethod
     def backward(ctx, g):
-        (dphi0,) = ctx.saved_tensors
+        run = ctx.run
+        if run is None:
+            raise RuntimeError("rollout: backward through a forward that kept no checkpoints")
+        dphi0, dsig, dM = run.backward()
+        ctx.run = None
         g = g.to(torch.float64)
-        return ((g * dphi0).to(torch.float32), (g * ctx.dsig).reshape(()), (g * ctx.dM).reshape(()),
+        dsig_t = torch.tensor(dsig, dtype=torch.float64, device=g.device)
+        dM_t = torch.tensor(dM, dtype=torch.float64, device=g.device)
+        return ((g * dphi0).to(torch.float32), (g * dsig_t).reshape(()), (g * dM_t).reshape(()),
                 None, None, None, None, None, None, None)
 
 
@@ -358,10 +405,19 @@ def rollout(phi0, sigma, M, params, form, T, target, ux0=None, uy0=None, every=N
     tension sigma and mobility M (other parameters from `params`), as a
     differentiable scalar: gradients w.r.t. phi0, sigma and M come from the
     hand-written adjoint with checkpoints every ceil(sqrt(T)) steps.  The
-    adjoint pass runs inside the forward call; backward only scales it."""
+    forward call runs the checkpointed forward pass only (none is kept when
+    no input needs a gradient, e.g. under torch.no_grad); the adjoint pass
+    runs in backward()."""
     if every is None:
         every = max(1, int(math.ceil(math.sqrt(T))))
     sig = sigma if torch.is_tensor(sigma) else torch.tensor(float(sigma), dtype=torch.float64)
     m = M if torch.is_tensor(M) else torch.tensor(float(M), dtype=torch.float64)
     pd = params if isinstance(params, dict) else {k: getattr(params, k) for k in params.__dataclass_fields__}
+    if not (torch.is_grad_enabled() and any(torch.is_tensor(t) and t.requires_grad for t in (phi0, sig, m))):
+        # nothing to differentiate: one plain forward pass, no checkpoints
+        p = dict(pd)
+        p["sigma"] = float(sig)
+        p["M"] = float(m)
+        run = _Checkpointed(p, form, int(T), phi0.detach().float(), target, ux0, uy0, int(every))
+        return torch.tensor(run.forward(keep_checkpoints=False), dtype=torch.float64, device=phi0.device)
     return _Rollout.apply(phi0, sig, m, pd, form, int(T), target, ux0, uy0, int(every))

@@ -163,6 +163,7 @@ struct lbm_sim {
   Phys c;
   char* ws;
   int cur;          // population buffer holding the current state
+  int shape;        // tile shape of the step kernels (index into kShapeTX/kShapeTY)
   int64_t step;
   int timing;
   // ring of event pairs per kernel: [kernel][slot][start/stop]; a slot is
@@ -273,6 +274,15 @@ int lbm_init(lbm_sim** out, const lbm_params* p, void* d_ws, size_t ws_bytes, co
   s->ws = (char*)d_ws;
   s->cur = 0;
   s->step = 0;
+  s->shape = 0;
+  if (const char* e = std::getenv("PFLBM_TILE")) {   // diagnostics: tile shape of a periodic lattice's step
+    const int sh = atoi(e);
+    if (sh < 0 || sh >= kNumShapes) {
+      delete s;
+      return fail(LBM_E_INVAL, "PFLBM_TILE must be 0..%d", kNumShapes - 1);
+    }
+    if (!p->wall_x && !p->wall_y) s->shape = sh;
+  }
   hipStream_t st = (hipStream_t)stream;
   Phys c = derive(p, 0.0);
   // node-local initial populations go to state array 1, the stored layout to array 0
@@ -310,12 +320,12 @@ int lbm_step(lbm_sim* s, int32_t nsteps, int32_t form, void* stream) {
     const bool timed = s->timing && s->step % s->timing == 0;
     if (timed)
       if (int r = timer_start(s, 0, st, &slot)) return r;
-    HIPCHK(launch_fused(form, a, st));
+    HIPCHK(launch_fused(form, s->shape, a, st));
     if (timed) {
       if (int r = timer_stop(s, 0, slot, st)) return r;
       if (int r = timer_start(s, 1, st, &slot)) return r;
     }
-    HIPCHK(launch_phi(a.sout, s->phi(), s->L.g, s->c.wall_x, s->c.wall_y, st));
+    HIPCHK(launch_phi(a.sout, s->phi(), s->L.g, s->c.wall_x, s->c.wall_y, s->shape, st));
     if (timed)
       if (int r = timer_stop(s, 1, slot, st)) return r;
     s->cur = 1 - s->cur;

@@ -71,12 +71,19 @@ struct BatchCfg {
   double ms;   // measured time per step (ms), 0 if not timed
 };
 
-int ntiles_of(const lbm_params& p) { return ((p.nx + kTX - 1) / kTX) * ((p.ny + kTY - 1) / kTY); }
+int tiles_x(const lbm_params& p, int shape) { return (p.nx + kShapeTX[shape] - 1) / kShapeTX[shape]; }
+int tiles_y(const lbm_params& p, int shape) { return (p.ny + kShapeTY[shape] - 1) / kShapeTY[shape]; }
+int ntiles_of(const lbm_params& p, int shape) { return tiles_x(p, shape) * tiles_y(p, shape); }
 
+// Room for the tile list of any shape: the most tiles any shape gives.
 BatchLayout layout(const lbm_params* p, int count) {
   BatchLayout L{};
   L.ntiles = 0;
-  for (int k = 0; k < count; ++k) L.ntiles += ntiles_of(p[k]);
+  for (int sh = 0; sh < kNumShapes; ++sh) {
+    int n = 0;
+    for (int k = 0; k < count; ++k) n += ntiles_of(p[k], sh);
+    L.ntiles = std::max(L.ntiles, n);
+  }
   size_t o = 0;
   L.desc = o; o = up(o + sizeof(BatchInst) * (size_t)count);
   L.tiles = o; o = up(o + sizeof(TileRef) * (size_t)L.ntiles);
@@ -126,6 +133,8 @@ struct lbm_batch {
   int parity;                    // population buffer holding the current state
   int64_t step;
   int cus;                       // compute units of the device
+  int shape;                     // tile shape of the step kernels (index into kShapeTX/kShapeTY)
+  int ntiles;                    // tiles of the list in use
   int form_beg[LBM_NUM_FORMS + 1];   // tile range of each force form in the sorted list
   BatchCfg cfg;                  // launch shape in use
   hipStream_t cap;               // private stream used only for graph capture
@@ -151,16 +160,16 @@ int launch_pair_steps(lbm_batch* b, const BatchCfg& c, int nsteps, int parity0, 
         const int t0 = b->form_beg[f], t1 = b->form_beg[f + 1];
         if (t1 > t0)
           BHIP(launch_batch_fused(b->d_inst(), b->d_tiles(), b->ws, t0, t1, f, c.fast, par, grid_for(b, c, t1 - t0),
-                                  st));
+                                  b->shape, st));
       }
     } else {
-      BHIP(launch_batch_fused(b->d_inst(), b->d_tiles(), b->ws, 0, b->L.ntiles, -1, c.fast, par,
-                              grid_for(b, c, b->L.ntiles), st));
+      BHIP(launch_batch_fused(b->d_inst(), b->d_tiles(), b->ws, 0, b->ntiles, -1, c.fast, par,
+                              grid_for(b, c, b->ntiles), b->shape, st));
     }
     // The order-parameter pass holds few registers: one workgroup per tile
     // keeps far more of them resident than the fused kernel's persistent grid.
-    BHIP(launch_batch_phi(b->d_inst(), b->d_tiles(), b->ws, b->L.ntiles, par,
-                          grid_for(b, BatchCfg{c.split, c.fast, 0, 0.0}, b->L.ntiles), st));
+    BHIP(launch_batch_phi(b->d_inst(), b->d_tiles(), b->ws, b->ntiles, par,
+                          grid_for(b, BatchCfg{c.split, c.fast, 0, 0.0}, b->ntiles), b->shape, st));
     par = 1 - par;
   }
   return LBM_OK;
@@ -181,10 +190,11 @@ int build_graph(lbm_batch* b) {
 }
 
 // Key of a batch for the tuning cache: device size, instance sizes, forms.
-uint64_t signature(const lbm_params* p, const int32_t* forms, int count, int cus) {
+uint64_t signature(const lbm_params* p, const int32_t* forms, int count, int cus, int shape) {
   uint64_t h = 1469598103934665603ull;
   auto mix = [&](uint64_t v) { h = (h ^ v) * 1099511628211ull; };
   mix((uint64_t)cus);
+  mix((uint64_t)shape);
   mix((uint64_t)count);
   for (int k = 0; k < count; ++k) {
     mix((uint64_t)p[k].nx);
@@ -262,7 +272,7 @@ int init_states(lbm_batch* b, const lbm_params* params, const float* const* d_ph
 // on this batch (the timing steps change the state; it is rebuilt after).
 int choose_cfg(lbm_batch* b, const lbm_params* params, const int32_t* forms, const float* const* d_phi0,
                hipStream_t st) {
-  const int occ = fused_blocks_per_cu();
+  const int occ = fused_blocks_per_cu(b->shape);
   const BatchCfg dflt{1, 1, occ, 0.0};
   if (const char* fc = std::getenv("PFLBM_BATCH_CFG")) {   // forced shape "split,fast,blocks_per_cu"
     BatchCfg c{0, 0, 0, 0.0};
@@ -277,7 +287,7 @@ int choose_cfg(lbm_batch* b, const lbm_params* params, const int32_t* forms, con
     b->cfg = dflt;
     return LBM_OK;
   }
-  const uint64_t key = signature(params, forms, b->count, b->cus);
+  const uint64_t key = signature(params, forms, b->count, b->cus, b->shape);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     read_tune_file();
@@ -344,6 +354,15 @@ int lbm_batch_create(lbm_batch** out, const lbm_params* params, const int32_t* f
   b->step = 0;
   b->cap = nullptr;
   b->exec = nullptr;
+  b->shape = 0;
+  if (const char* e = std::getenv("PFLBM_BATCH_SHAPE")) {   // diagnostics: force a tile shape
+    const int sh = atoi(e);
+    if (sh < 0 || sh >= kNumShapes) {
+      delete b;
+      return bfail(LBM_E_INVAL, "PFLBM_BATCH_SHAPE must be 0..%d", kNumShapes - 1);
+    }
+    b->shape = sh;
+  }
   hipStream_t st = (hipStream_t)stream;
   auto cleanup = [&](int code) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -391,11 +410,12 @@ int lbm_batch_create(lbm_batch** out, const lbm_params* params, const int32_t* f
   tiles.reserve(b->L.ntiles);
   for (int f = 0; f <= LBM_NUM_FORMS; ++f) b->form_beg[f] = 0;
   for (int k : order) {
-    for (int f = forms[k] + 1; f <= LBM_NUM_FORMS; ++f) b->form_beg[f] += ntiles_of(params[k]);
-    const int ntx = (params[k].nx + kTX - 1) / kTX, nty = (params[k].ny + kTY - 1) / kTY;
+    for (int f = forms[k] + 1; f <= LBM_NUM_FORMS; ++f) b->form_beg[f] += ntiles_of(params[k], b->shape);
+    const int ntx = tiles_x(params[k], b->shape), nty = tiles_y(params[k], b->shape);
     for (int ty = 0; ty < nty; ++ty)
       for (int tx = 0; tx < ntx; ++tx) tiles.push_back(TileRef{k, tx, ty, 0});
   }
+  b->ntiles = (int)tiles.size();
   if (hipMemcpyAsync(ws + b->L.desc, b->host.data(), sizeof(BatchInst) * count, hipMemcpyHostToDevice, st) !=
           hipSuccess ||
       hipMemcpyAsync(ws + b->L.tiles, tiles.data(), sizeof(TileRef) * tiles.size(), hipMemcpyHostToDevice, st) !=

@@ -36,9 +36,12 @@ constexpr int kNPL = 21;  // planes of a state array
 constexpr int kPF = 0, kPH = 9, kPP = 18, kPJ = 19;   // first plane of f, h, P, J
 constexpr int kSegE = kNPL * 64;   // elements of one interleaved row segment
 
-constexpr int kTX = 64;   // tile width  (one wavefront row)
-constexpr int kTY = 8;    // tile height
-constexpr int kThreads = 256;
+// Tile shapes of the fused and order-parameter kernels (TX x TY nodes, one
+// node per thread), by index: 0 is the single-lattice shape, all four are
+// candidates of the batched step's tuner.
+constexpr int kNumShapes = 4;
+constexpr int kShapeTX[kNumShapes] = {64, 32, 32, 64};
+constexpr int kShapeTY[kNumShapes] = {8, 16, 8, 4};
 
 // Per-simulation physical constants in the form the kernels use.
 struct Phys {
@@ -103,7 +106,7 @@ struct BatchInst {
   int pad[3];
 };
 
-// One 64x8 tile of one instance.
+// One tile of one instance (tile indices in units of the batch's tile shape).
 struct TileRef {
   int inst, tx, ty, pad;
 };
@@ -131,9 +134,9 @@ Phys sim_phys(const lbm_sim* s);
 int sim_view(const lbm_sim* s, SimView* v);
 
 // kernel launchers (lbm_kernels.hip); each returns the launch error code
-hipError_t launch_fused(int form, const StepArgs& a, hipStream_t s);
+hipError_t launch_fused(int form, int shape, const StepArgs& a, hipStream_t s);
 hipError_t launch_moments(int form, const StepArgs& a, const MomentArgs& m, hipStream_t s);
-hipError_t launch_phi(const float* snew, double* phi, const Grid& g, int wall_x, int wall_y, hipStream_t s);
+hipError_t launch_phi(const float* snew, double* phi, const Grid& g, int wall_x, int wall_y, int shape, hipStream_t s);
 hipError_t launch_init(const float* phi0, const float* ux0, const float* uy0, float* s_tmp, float* s0, double* phi,
                        const Grid& g, const Phys& c, hipStream_t s);
 hipError_t launch_phi_sum(const double* phi, const Grid& g, double* partial, int npartial, double* out,
@@ -146,9 +149,9 @@ hipError_t launch_copies(const void* const* src, void* const* dst, const size_t*
 // persistent batched step kernels over a tile list (periodic instances); form < 0:
 // one kernel for every form, else the tiles [t0, t1) all have that form
 hipError_t launch_batch_fused(const BatchInst* inst, const TileRef* tiles, char* ws, int t0, int t1, int form,
-                              int fast, int parity, int nblocks, hipStream_t s);
+                              int fast, int parity, int nblocks, int shape, hipStream_t s);
 hipError_t launch_batch_phi(const BatchInst* inst, const TileRef* tiles, char* ws, int ntiles, int parity, int nblocks,
-                            hipStream_t s);
-int fused_blocks_per_cu();
+                            int shape, hipStream_t s);
+int fused_blocks_per_cu(int shape);
 
 }  // namespace pflbm

@@ -7,9 +7,11 @@
 //                  d_t(phi u), collide both populations and store them.
 //   k_phi          phi^{n+1} = phi^n + d0 + sum_{i>=1} h_i pulled, in FP64.
 //
-// The fused kernel works on 64x8 tiles.  The order parameter is staged in LDS
-// with a 3-node halo (FP64); second-level stencil fields live on the 2-node
-// ring, the velocity on the 1-node ring.  Only nearest-neighbour pulls touch
+// The fused kernel works on TX x TY tiles, one node per thread (the tile
+// shape is a template parameter: 64x8 for single lattices, a choice of shapes
+// for the batched step).  The order parameter is staged in LDS with a 3-node
+// halo (FP64); second-level stencil fields live on the 2-node ring, the
+// velocity on the 1-node ring.  Only nearest-neighbour pulls touch
 // HBM; everything with a wider footprint comes from LDS.  The state arrays
 // interleave their 21 planes in 64-node row segments (lbm_internal.hpp), so a
 // wavefront's loads and stores of one row segment form one contiguous run.
@@ -19,13 +21,23 @@ namespace pflbm {
 
 namespace {
 
-constexpr int PW = kTX + 6, PH = kTY + 6;   // phi tile (halo 3)
-constexpr int BW = kTX + 4, BH = kTY + 4;   // second-level fields (halo 2)
-constexpr int UW = kTX + 2, UH = kTY + 2;   // velocity ring (halo 1)
-constexpr int NRING = 2 * UW + 2 * kTY;     // positions of the velocity ring
 constexpr float CS2 = 1.0f / 3.0f;
-constexpr int kFusedThreads = kTX * kTY;   // one node per thread
 constexpr int kXcds = 8;                    // accelerator complex dies of the MI355X
+
+// Tile shape of the fused and order-parameter kernels: TX x TY nodes, one
+// per thread.  TX is 32 or 64 (a wavefront covers one or two tile rows, each
+// a run inside one 64-node row segment of the state arrays).
+template <int TX_, int TY_>
+struct Shape {
+  static constexpr int TX = TX_, TY = TY_, NT = TX_ * TY_;
+  static constexpr int PW = TX + 6, PH = TY + 6;   // phi tile (halo 3)
+  static constexpr int BW = TX + 4, BH = TY + 4;   // second-level fields (halo 2)
+  static constexpr int UW = TX + 2, UH = TY + 2;   // velocity ring (halo 1)
+  static constexpr int NRING = 2 * UW + 2 * TY;    // positions of the velocity ring
+  static constexpr int NPHI = (PW * PH + NT - 1) / NT;   // phi values a thread stages
+  static_assert(TX == 32 || TX == 64, "a tile row is half or all of a 64-node row segment");
+  static_assert(NRING <= NT && NPHI <= 3, "one ring position and at most three phi values per thread");
+};
 
 __device__ __forceinline__ int wrap_or_reflect(int c, int n, int wall) {
   if (wall) {
@@ -145,16 +157,18 @@ __device__ __forceinline__ double rcp64(double x) {
 __device__ __forceinline__ double rho_of(double phi, const Phys& c) { return c.rho2_d + c.drho_half_d * (1.0 + phi); }
 __device__ __forceinline__ double mu_of(double phi, const Phys& c) { return c.mu2_d + c.dmu_half_d * (1.0 + phi); }
 
+template <class S>
 struct Lds {
-  double phi[PH][PW];
-  double gl[3][BH][BW];   // grad phi (x, y) and lap phi on the 2-ring
-  double b[3][BH][BW];
-  float q[2][UH][UW];   // phi u on the tile and its 1-node ring
+  double phi[S::PH][S::PW];
+  double gl[3][S::BH][S::BW];   // grad phi (x, y) and lap phi on the 2-ring
+  double b[3][S::BH][S::BW];
+  float q[2][S::UH][S::UW];     // phi u on the tile and its 1-node ring
 };
 
 // gradient and Laplacian of phi at sPhi position (py, px) (Eqs. 41-42), in
 // FP64 from differences to the centre value.
-__device__ __forceinline__ void grad_lap_phi(const Lds& s, int py, int px, double& gx, double& gy, double& lap) {
+template <class S>
+__device__ __forceinline__ void grad_lap_phi(const Lds<S>& s, int py, int px, double& gx, double& gy, double& lap) {
   const double c = s.phi[py][px];
   double sx = 0.0, sy = 0.0, sl = 0.0;
 #pragma unroll
@@ -175,6 +189,7 @@ __device__ __forceinline__ double chem_pot(double phi, double lap, const Phys& c
 }
 
 // isotropic gradient of an LDS field at (by, bx)  (Eq. 41)
+template <int BW>
 __device__ __forceinline__ void grad_b(const double (*f)[BW], int by, int bx, double& gx, double& gy) {
   const double c = f[by][bx];
   double sx = 0.0, sy = 0.0;
@@ -190,11 +205,11 @@ __device__ __forceinline__ void grad_b(const double (*f)[BW], int by, int bx, do
 
 // Stage B: form-specific node field(s) on the 2-ring (FP64: their stencil
 // differences are small against their values).
-template <int FORM>
-__device__ __forceinline__ void stage_b(Lds& s, int tid, const Phys& c) {
+template <int FORM, class S>
+__device__ __forceinline__ void stage_b(Lds<S>& s, int tid, const Phys& c) {
   const double kappa = c.kappa_d;
-  for (int k = tid; k < BH * BW; k += kFusedThreads) {
-    const int by = k / BW, bx = k - by * BW;
+  for (int k = tid; k < S::BH * S::BW; k += S::NT) {
+    const int by = k / S::BW, bx = k - by * S::BW;
     const int py = by + 1, px = bx + 1;
     double gx, gy, lap;
     grad_lap_phi(s, py, px, gx, gy, lap);
@@ -225,8 +240,8 @@ __device__ __forceinline__ void stage_b(Lds& s, int tid, const Phys& c) {
 
 // Interfacial force at velocity-ring position (uy_, ux_) (Sec. II.B), in FP64.
 // sPhi index of that node is (uy_ + 2, ux_ + 2); stage-B index (uy_ + 1, ux_ + 1).
-template <int FORM>
-__device__ __forceinline__ void force_sf(const Lds& s, int uy_, int ux_, const Phys& c, double& fxo, double& fyo) {
+template <int FORM, class S>
+__device__ __forceinline__ void force_sf(const Lds<S>& s, int uy_, int ux_, const Phys& c, double& fxo, double& fyo) {
   const int py = uy_ + 2, px = ux_ + 2, by = uy_ + 1, bx = ux_ + 1;
   const double kappa = c.kappa_d;
   double fx, fy;
@@ -316,11 +331,11 @@ __device__ __forceinline__ void load_fp(const StepArgs& a, int x, int y, float* 
 // velocity-ring position is (uy_, ux_).  The stored flow populations are
 // deviations from the pressure of the node that stored them:
 // f_i = ft_i + w_i ps_i.
-template <int FORM, bool FULL>
-__device__ __forceinline__ void velocity_from(const Lds& s, const StepArgs& a, int uy_, int ux_, const float* ft,
+template <int FORM, bool FULL, class S>
+__device__ __forceinline__ void velocity_from(const Lds<S>& s, const StepArgs& a, int uy_, int ux_, const float* ft,
                                               const float* ps, NodeState& ns) {
   double fx, fy;
-  force_sf<FORM>(s, uy_, ux_, a.c, fx, fy);
+  force_sf<FORM, S>(s, uy_, ux_, a.c, fx, fy);
   const double phid = s.phi[uy_ + 2][ux_ + 2];
   const double rho = rho_of(phid, a.c);
   fx += (rho - a.c.rho0_d) * a.c.gx_d;   // F_g = (rho - rho0) g   (Eq. 8)
@@ -363,8 +378,8 @@ __device__ __forceinline__ void velocity_from(const Lds& s, const StepArgs& a, i
 // Eq. 21 for CPF and PF; zero for STF-2 and CSF).  STF-1 takes
 // -kappa |grad phi|^2, the value Eqs. (19) and (26) give (the sign printed
 // with Eq. 17 contradicts them).  f0 = beta (1 - phi^2)^2.
-template <int FORM>
-__device__ __forceinline__ double pressure_offset(const Lds& s, int uy_, int ux_, const Phys& c) {
+template <int FORM, class S>
+__device__ __forceinline__ double pressure_offset(const Lds<S>& s, int uy_, int ux_, const Phys& c) {
   const double phi = s.phi[uy_ + 2][ux_ + 2];
   const double gx = s.gl[0][uy_ + 1][ux_ + 1], gy = s.gl[1][uy_ + 1][ux_ + 1], lap = s.gl[2][uy_ + 1][ux_ + 1];
   const double kg2 = c.kappa_d * (gx * gx + gy * gy);
@@ -381,11 +396,12 @@ __device__ __forceinline__ double pressure_offset(const Lds& s, int uy_, int ux_
 __device__ __forceinline__ bool in_domain(int x, int y, const Grid& g) { return x >= 0 && x < g.nx && y >= 0 && y < g.ny; }
 
 // Velocity-ring position k -> (uy_, ux_)
+template <class S>
 __device__ __forceinline__ void ring_pos(int k, int& uy_, int& ux_) {
-  if (k < UW) { uy_ = 0; ux_ = k; }
-  else if (k < 2 * UW) { uy_ = UH - 1; ux_ = k - UW; }
-  else if (k < 2 * UW + kTY) { uy_ = k - 2 * UW + 1; ux_ = 0; }
-  else { uy_ = k - 2 * UW - kTY + 1; ux_ = UW - 1; }
+  if (k < S::UW) { uy_ = 0; ux_ = k; }
+  else if (k < 2 * S::UW) { uy_ = S::UH - 1; ux_ = k - S::UW; }
+  else if (k < 2 * S::UW + S::TY) { uy_ = k - 2 * S::UW + 1; ux_ = 0; }
+  else { uy_ = k - 2 * S::UW - S::TY + 1; ux_ = S::UW - 1; }
 }
 
 // Global position of ring position, wrapped on periodic axes; returns false
@@ -442,8 +458,9 @@ __device__ __forceinline__ void load_fp_tile(const float* tin, int rowe, const u
 
 // A tile is interior when every position it reads (the phi halo reaches 3
 // nodes past the tile) lies inside the domain: no wrap, mirror or bounce.
+template <class S>
 __device__ __forceinline__ bool interior_tile(int x0, int y0, const Grid& g) {
-  return g.fast && x0 >= 3 && y0 >= 3 && x0 + kTX + 3 <= g.nx && y0 + kTY + 3 <= g.ny;
+  return g.fast && x0 >= 3 && y0 >= 3 && x0 + S::TX + 3 <= g.nx && y0 + S::TY + 3 <= g.ny;
 }
 
 // Wall term of Eq. (43) for a population leaving node (x, y) in direction
@@ -498,15 +515,16 @@ __device__ __forceinline__ int tile_tid() {
   return t;
 }
 
-// One 64x8 tile of the step (or of the moments): the whole per-node update
-// of a1-a12.  FAST: an interior tile (see interior_tile), step only.
-template <int FORM, bool MOMENTS, int BC, bool FAST, bool LOOPED = false>
-__device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const MomentArgs& m, int tile_x, int tile_y) {
+// One tile of the step (or of the moments): the whole per-node update of
+// a1-a12.  FAST: an interior tile (see interior_tile), step only.
+template <class S, int FORM, bool MOMENTS, int BC, bool FAST, bool LOOPED>
+__device__ __forceinline__ void tile_impl(Lds<S>& s, const StepArgs& a, const MomentArgs& m, int tile_x, int tile_y) {
   static_assert(!(FAST && MOMENTS), "the moments use the general path");
   constexpr bool WX = (BC & 1) != 0, WY = (BC & 2) != 0;   // walled axes (compile time)
   const int tid = tile_tid<LOOPED>();
-  const int x0 = tile_x * kTX, y0 = tile_y * kTY;
-  const int lx = tid & (kTX - 1), ty = tid / kTX;   // one node per thread
+  constexpr int PW = S::PW, PH = S::PH, NT = S::NT;
+  const int x0 = tile_x * S::TX, y0 = tile_y * S::TY;
+  const int lx = tid & (S::TX - 1), ty = tid / S::TX;   // one node per thread
   const Grid& g = a.g;
   const Phys& c = a.c;
   const int uy_ = ty + 1, ux_ = lx + 1;             // velocity-ring coordinates of this node
@@ -545,38 +563,46 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
   bool ring_ok = true;   // general path: the ring position is not beyond a wall
   // Stage A: phi tile with a 3-node halo (periodic wrap / even reflection at walls, Sec. IV)
   if constexpr (FAST) {
-    // both loads of a thread in flight before either is stored
-    static_assert(PH * PW > kFusedThreads && PH * PW <= 2 * kFusedThreads, "two phi values per thread");
+    // every load of a thread in flight before any is stored
     const double* tphi = a.phi + ((long long)(y0 - 3) * g.pitch + (x0 - 3));
-    const int k1 = tid + kFusedThreads;
-    const int py0 = tid / PW, px0 = tid - py0 * PW, py1 = k1 / PW, px1 = k1 - py1 * PW;
-    const double p0 = *at(tphi, (unsigned)(py0 * g.pitch + px0) * 8u);
-    const double p1 = k1 < PH * PW ? *at(tphi, (unsigned)(py1 * g.pitch + px1) * 8u) : 0.0;
-    s.phi[py0][px0] = p0;
-    if (k1 < PH * PW) s.phi[py1][px1] = p1;
+    double pv[S::NPHI];
+#pragma unroll
+    for (int j = 0; j < S::NPHI; ++j) {
+      const int k = tid + j * NT, py = k / PW, px = k - py * PW;
+      pv[j] = (j == 0 || k < PH * PW) ? *at(tphi, (unsigned)(py * g.pitch + px) * 8u) : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < S::NPHI; ++j) {
+      const int k = tid + j * NT, py = k / PW, px = k - py * PW;
+      if (j == 0 || k < PH * PW) s.phi[py][px] = pv[j];
+    }
     if constexpr (!MOMENTS) {
-      if (tid < NRING) {
-        ring_pos(tid, ruy, rux);
+      if (tid < S::NRING) {
+        ring_pos<S>(tid, ruy, rux);
         unsigned rv[3];
         node_offsets(g, x0, rux - 1, ruy - 1, rv);
         load_fp_tile<false>(tin, g.rowe, rv, rft, rps);
       }
     }
   } else {
-    // the same order as on interior tiles: both phi loads, the stores, then
+    // the same order as on interior tiles: the phi loads, the stores, then
     // the ring's pulls, which stay in flight through the stencil stage
-    const int k1 = tid + kFusedThreads;
-    const int py0 = tid / PW, px0 = tid - py0 * PW, py1 = k1 / PW, px1 = k1 - py1 * PW;
-    const double p0 =
-        a.phi[(unsigned)(halo_coord<WY>(y0 + py0 - 3, g.ny) * g.pitch + halo_coord<WX>(x0 + px0 - 3, g.nx))];
-    const double p1 = k1 < PH * PW ? a.phi[(unsigned)(halo_coord<WY>(y0 + py1 - 3, g.ny) * g.pitch +
-                                                      halo_coord<WX>(x0 + px1 - 3, g.nx))]
-                                   : 0.0;
-    s.phi[py0][px0] = p0;
-    if (k1 < PH * PW) s.phi[py1][px1] = p1;
+    double pv[S::NPHI];
+#pragma unroll
+    for (int j = 0; j < S::NPHI; ++j) {
+      const int k = tid + j * NT, py = k / PW, px = k - py * PW;
+      pv[j] = (j == 0 || k < PH * PW)
+                  ? a.phi[(unsigned)(halo_coord<WY>(y0 + py - 3, g.ny) * g.pitch + halo_coord<WX>(x0 + px - 3, g.nx))]
+                  : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < S::NPHI; ++j) {
+      const int k = tid + j * NT, py = k / PW, px = k - py * PW;
+      if (j == 0 || k < PH * PW) s.phi[py][px] = pv[j];
+    }
     if constexpr (!MOMENTS) {
-      if (tid < NRING) {
-        ring_pos(tid, ruy, rux);
+      if (tid < S::NRING) {
+        ring_pos<S>(tid, ruy, rux);
         int rx, ry;
         ring_ok = ring_global<WX, WY>(ruy, rux, x0, y0, a, rx, ry);
         if (ring_ok) load_fp<WX, WY>(a, rx, ry, rft, rps);
@@ -585,7 +611,7 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
   }
   __syncthreads();
 
-  stage_b<FORM>(s, tid, c);
+  stage_b<FORM, S>(s, tid, c);
   __syncthreads();
 
   // Stage C: velocities of the ring (step only), then of this node.  On
@@ -601,10 +627,10 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
   if constexpr (FAST) node_offsets(g, x0, lx, ty, v3);
   if constexpr (kEarlyOwn) load_fp_tile<true>(tin, g.rowe, v3, ft, ps);
   if constexpr (!MOMENTS) {
-    if (tid < NRING) {
+    if (tid < S::NRING) {
       if (FAST || ring_ok) {
         NodeState rs;
-        velocity_from<FORM, false>(s, a, ruy, rux, rft, rps, rs);
+        velocity_from<FORM, false, S>(s, a, ruy, rux, rft, rps, rs);
         const double ph = s.phi[ruy + 2][rux + 2];
         s.q[0][ruy][rux] = (float)(ph * rs.ux);
         s.q[1][ruy][rux] = (float)(ph * rs.uy);
@@ -615,7 +641,7 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
   if (valid) {
     if constexpr (!FAST) load_fp<WX, WY>(a, x, y, ft, ps);
     else if constexpr (!kEarlyOwn) load_fp_tile<true>(tin, g.rowe, v3, ft, ps);
-    velocity_from<FORM, true>(s, a, uy_, ux_, ft, ps, n);
+    velocity_from<FORM, true, S>(s, a, uy_, ux_, ft, ps, n);
     if constexpr (!MOMENTS) {
       const double ph = s.phi[uy_ + 2][ux_ + 2];
       s.q[0][uy_][ux_] = (float)(ph * n.ux);
@@ -630,7 +656,7 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
       if (m.ux) m.ux[om] = (float)n.ux;
       if (m.uy) m.uy[om] = (float)n.uy;
       if (m.p) m.p[om] = (float)n.P;
-      if (m.ph) m.ph[om] = (float)(n.P - pressure_offset<FORM>(s, uy_, ux_, c));
+      if (m.ph) m.ph[om] = (float)(n.P - pressure_offset<FORM, S>(s, uy_, ux_, c));
     }
     return;
   } else {
@@ -740,8 +766,8 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
     //   K1 = rho/(3 tau_f) - k u.F - k u.grad(rho)/3.
     // Directions come in opposite pairs (c_J = -c_I): s = e +- o with the
     // even part e = 4.5 (c.u)^2 - 1.5 u^2 and the odd part o = 3 c.u, so
-    // f_I^+, f_J^+ = keep f + w (S +- Q) with S = K0 + e K1 + o d,
-    // Q = c.kF + e d + o K1, d = c.kF + c.kG.  Likewise h_I^+, h_J^+ =
+    // f_I^+, f_J^+ = keep f + w (Se +- Qo) with Se = K0 + e K1 + o d,
+    // Qo = c.kF + e d + o K1, d = c.kF + c.kG.  Likewise h_I^+, h_J^+ =
     // keep h + w (G0 +- 3 c.V).
     const double fx = (double)n.fx, fy = (double)n.fy, grx = (double)n.grx, gry = (double)n.gry;
     const double uF = n.ux * fx + n.uy * fy, uG = n.ux * grx + n.uy * gry;
@@ -762,8 +788,8 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
     const double cu = dotc(I, n.ux, n.uy);                                                     \
     const double e = fma(4.5 * cu, cu, m15usq), od = 3.0 * cu;                                 \
     const double cF = dotc(I, kFx, kFy), d = dotc(I, kFGx, kFGy);                              \
-    const double S = fma(od, d, fma(e, K1, K0)), Q = fma(od, K1, fma(e, d, cF));               \
-    const double wS = wtd(I) * S, wQ = wtd(I) * Q;                                             \
+    const double Se = fma(od, d, fma(e, K1, K0)), Qo = fma(od, K1, fma(e, d, cF));             \
+    const double wS = wtd(I) * Se, wQ = wtd(I) * Qo;                                           \
     const double fpi = fma(keep_f, (double)n.f[I], wS + wQ);                                   \
     const double fpj = fma(keep_f, (double)n.f[J_], wS - wQ);                                  \
     const double wG = wtd(I) * G0, t = (3.0 * wtd(I)) * dotc(I, Vx, Vy);                      \
@@ -781,40 +807,40 @@ __device__ __forceinline__ void tile_impl(Lds& s, const StepArgs& a, const Momen
   }
 }
 
-template <int FORM, bool MOMENTS, int BC, bool LOOPED = false>
-__device__ __forceinline__ void fused_tile(Lds& s, const StepArgs& a, const MomentArgs& m, int tile_x, int tile_y) {
+template <class S, int FORM, bool MOMENTS, int BC, bool LOOPED>
+__device__ __forceinline__ void fused_tile(Lds<S>& s, const StepArgs& a, const MomentArgs& m, int tile_x, int tile_y) {
   if constexpr (!MOMENTS) {
-    if (interior_tile(tile_x * kTX, tile_y * kTY, a.g)) {
-      tile_impl<FORM, false, BC, true, LOOPED>(s, a, m, tile_x, tile_y);
+    if (interior_tile<S>(tile_x * S::TX, tile_y * S::TY, a.g)) {
+      tile_impl<S, FORM, false, BC, true, LOOPED>(s, a, m, tile_x, tile_y);
       return;
     }
   }
-  tile_impl<FORM, MOMENTS, BC, false, LOOPED>(s, a, m, tile_x, tile_y);
+  tile_impl<S, FORM, MOMENTS, BC, false, LOOPED>(s, a, m, tile_x, tile_y);
 }
 
-template <int FORM, bool MOMENTS, int BC>
-__global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_fused(StepArgs a, MomentArgs m) {
-  __shared__ Lds s;
+template <class S, int FORM, bool MOMENTS, int BC>
+__global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(4))) void k_fused(StepArgs a, MomentArgs m) {
+  __shared__ Lds<S> s;
   int tile_x, tile_y;
-  if (!xcd_tile((a.g.nx + kTX - 1) / kTX, (a.g.ny + kTY - 1) / kTY, tile_x, tile_y)) return;
-  fused_tile<FORM, MOMENTS, BC>(s, a, m, tile_x, tile_y);
+  if (!xcd_tile((a.g.nx + S::TX - 1) / S::TX, (a.g.ny + S::TY - 1) / S::TY, tile_x, tile_y)) return;
+  fused_tile<S, FORM, MOMENTS, BC, false>(s, a, m, tile_x, tile_y);
 }
 
 // phi^{n+1}(x) = phi^n(x) + d0(x) + sum_{i>=1} h_i^+(x - c_i)   (Eq. 37,
 // phi = sum h_i), from the state array just written (snew).  Both paths sum
 // in the same order.
-template <int BC, bool FAST>
+template <class S, int BC, bool FAST>
 __device__ __forceinline__ void phi_tile_impl(const float* __restrict__ snew, double* __restrict__ phi, const Grid& g,
                                               int tile_x, int tile_y) {
   constexpr int wx = (BC & 1) != 0, wy = (BC & 2) != 0;
-  const int lx = threadIdx.x & (kTX - 1), ty = threadIdx.x / kTX;
-  const int x = tile_x * kTX + lx, y = tile_y * kTY + ty;
+  const int lx = threadIdx.x & (S::TX - 1), ty = threadIdx.x / S::TX;
+  const int x = tile_x * S::TX + lx, y = tile_y * S::TY + ty;
   if (x >= g.nx || y >= g.ny) return;
   double sum;
   if constexpr (FAST) {
-    const float* tin = snew + nbase(g, tile_xo(tile_x * kTX), tile_y * kTY - 2);
+    const float* tin = snew + nbase(g, tile_xo(tile_x * S::TX), tile_y * S::TY - 2);
     unsigned v3[3];
-    node_offsets(g, tile_x * kTX, lx, ty, v3);
+    node_offsets(g, tile_x * S::TX, lx, ty, v3);
     sum = (double)pull_tile<0, kPH, true>(tin, g.rowe, v3);
     sum += (double)pull_tile<1, kPH + 1, true>(tin, g.rowe, v3);
     sum += (double)pull_tile<2, kPH + 2, true>(tin, g.rowe, v3);
@@ -838,17 +864,17 @@ __device__ __forceinline__ void phi_tile_impl(const float* __restrict__ snew, do
   phi[(long long)y * g.pitch + x] += sum;
 }
 
-template <int BC>
+template <class S, int BC>
 __device__ __forceinline__ void phi_tile(const float* snew, double* phi, const Grid& g, int tile_x, int tile_y) {
-  if (interior_tile(tile_x * kTX, tile_y * kTY, g)) phi_tile_impl<BC, true>(snew, phi, g, tile_x, tile_y);
-  else phi_tile_impl<BC, false>(snew, phi, g, tile_x, tile_y);
+  if (interior_tile<S>(tile_x * S::TX, tile_y * S::TY, g)) phi_tile_impl<S, BC, true>(snew, phi, g, tile_x, tile_y);
+  else phi_tile_impl<S, BC, false>(snew, phi, g, tile_x, tile_y);
 }
 
-template <int BC>
-__global__ __launch_bounds__(kFusedThreads) void k_phi(const float* __restrict__ snew, double* __restrict__ phi, Grid g) {
+template <class S, int BC>
+__global__ __launch_bounds__(S::NT) void k_phi(const float* __restrict__ snew, double* __restrict__ phi, Grid g) {
   int tx, ty;
-  if (!xcd_tile((g.nx + kTX - 1) / kTX, (g.ny + kTY - 1) / kTY, tx, ty)) return;
-  phi_tile<BC>(snew, phi, g, tx, ty);
+  if (!xcd_tile((g.nx + S::TX - 1) / S::TX, (g.ny + S::TY - 1) / S::TY, tx, ty)) return;
+  phi_tile<S, BC>(snew, phi, g, tx, ty);
 }
 
 // Batched step: persistent workgroups walk a tile list covering every
@@ -867,10 +893,10 @@ __device__ __forceinline__ void band(int t0, int t1, int& first, int& end, int& 
 // One tile of instance descriptor bi: FAST_OK lets interior tiles take the
 // interior addressing path (more registers); otherwise every tile takes the
 // general one.
-template <int FORM, bool FAST_OK>
-__device__ __forceinline__ void batch_tile(Lds& s, const StepArgs& a, int tx, int ty) {
-  if constexpr (FAST_OK) fused_tile<FORM, false, 0, true>(s, a, MomentArgs{}, tx, ty);
-  else tile_impl<FORM, false, 0, false, true>(s, a, MomentArgs{}, tx, ty);
+template <class S, int FORM, bool FAST_OK>
+__device__ __forceinline__ void batch_tile(Lds<S>& s, const StepArgs& a, int tx, int ty) {
+  if constexpr (FAST_OK) fused_tile<S, FORM, false, 0, true>(s, a, MomentArgs{}, tx, ty);
+  else tile_impl<S, FORM, false, 0, false, true>(s, a, MomentArgs{}, tx, ty);
 }
 
 // Step arguments of a batch instance with its pointers rebuilt from the
@@ -888,10 +914,10 @@ __device__ __forceinline__ StepArgs batch_args(const BatchInst& bi, int parity, 
 
 // FORM >= 0: every tile of [t0, t1) has that force form (the tile list is
 // sorted by form); FORM < 0: any form, dispatched per tile.
-template <int FORM, bool FAST_OK>
-__global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_fused(
+template <class S, int FORM, bool FAST_OK>
+__global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_fused(
     const BatchInst* __restrict__ inst, const TileRef* __restrict__ tiles, char* ws, int t0, int t1, int parity) {
-  __shared__ Lds s;
+  __shared__ Lds<S> s;
   int first, end, stride;
   band(t0, t1, first, end, stride);
   for (int t = first; t < end; t += stride) {
@@ -900,31 +926,32 @@ __global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(4
     __syncthreads();   // the previous tile is done with the LDS
     const StepArgs a = batch_args(bi, parity, ws);
     if constexpr (FORM >= 0) {
-      batch_tile<FORM, FAST_OK>(s, a, tr.tx, tr.ty);
+      batch_tile<S, FORM, FAST_OK>(s, a, tr.tx, tr.ty);
     } else {
       switch (bi.form) {
-        case 0: batch_tile<0, FAST_OK>(s, a, tr.tx, tr.ty); break;
-        case 1: batch_tile<1, FAST_OK>(s, a, tr.tx, tr.ty); break;
-        case 2: batch_tile<2, FAST_OK>(s, a, tr.tx, tr.ty); break;
-        case 3: batch_tile<3, FAST_OK>(s, a, tr.tx, tr.ty); break;
-        case 4: batch_tile<4, FAST_OK>(s, a, tr.tx, tr.ty); break;
-        case 5: batch_tile<5, FAST_OK>(s, a, tr.tx, tr.ty); break;
-        case 6: batch_tile<6, FAST_OK>(s, a, tr.tx, tr.ty); break;
-        default: batch_tile<7, FAST_OK>(s, a, tr.tx, tr.ty); break;
+        case 0: batch_tile<S, 0, FAST_OK>(s, a, tr.tx, tr.ty); break;
+        case 1: batch_tile<S, 1, FAST_OK>(s, a, tr.tx, tr.ty); break;
+        case 2: batch_tile<S, 2, FAST_OK>(s, a, tr.tx, tr.ty); break;
+        case 3: batch_tile<S, 3, FAST_OK>(s, a, tr.tx, tr.ty); break;
+        case 4: batch_tile<S, 4, FAST_OK>(s, a, tr.tx, tr.ty); break;
+        case 5: batch_tile<S, 5, FAST_OK>(s, a, tr.tx, tr.ty); break;
+        case 6: batch_tile<S, 6, FAST_OK>(s, a, tr.tx, tr.ty); break;
+        default: batch_tile<S, 7, FAST_OK>(s, a, tr.tx, tr.ty); break;
       }
     }
   }
 }
 
-__global__ __launch_bounds__(kFusedThreads) void k_batch_phi(const BatchInst* __restrict__ inst,
-                                                             const TileRef* __restrict__ tiles, char* ws, int ntiles,
-                                                             int parity) {
+template <class S>
+__global__ __launch_bounds__(S::NT) void k_batch_phi(const BatchInst* __restrict__ inst,
+                                                     const TileRef* __restrict__ tiles, char* ws, int ntiles,
+                                                     int parity) {
   int first, end, stride;
   band(0, ntiles, first, end, stride);
   for (int t = first; t < end; t += stride) {
     const TileRef tr = tiles[t];
     const StepArgs a = batch_args(inst[tr.inst], parity, ws);
-    phi_tile<0>(a.sout, const_cast<double*>(a.phi), a.g, tr.tx, tr.ty);
+    phi_tile<S, 0>(a.sout, const_cast<double*>(a.phi), a.g, tr.tx, tr.ty);
   }
 }
 
@@ -1064,57 +1091,88 @@ __global__ void k_fill_int(int* p, int v, int n) {
   if (k < n) p[k] = v;
 }
 
-template <int FORM, int BC>
+// Tile shapes by index (kShapeTX/kShapeTY in lbm_internal.hpp).
+using S0 = Shape<kShapeTX[0], kShapeTY[0]>;
+using S1 = Shape<kShapeTX[1], kShapeTY[1]>;
+using S2 = Shape<kShapeTX[2], kShapeTY[2]>;
+using S3 = Shape<kShapeTX[3], kShapeTY[3]>;
+
+template <class S>
+dim3 tile_grid(const Grid& g) {
+  const int ntiles = ((g.nx + S::TX - 1) / S::TX) * ((g.ny + S::TY - 1) / S::TY);
+  return dim3((ntiles + kXcds - 1) / kXcds * kXcds);
+}
+
+template <class S, int FORM, int BC>
 hipError_t launch_fused_t(const StepArgs& a, const MomentArgs& m, bool moments, hipStream_t st) {
-  const int ntiles = ((a.g.nx + kTX - 1) / kTX) * ((a.g.ny + kTY - 1) / kTY);
-  dim3 grid((ntiles + kXcds - 1) / kXcds * kXcds);
-  if (moments) hipLaunchKernelGGL((k_fused<FORM, true, BC>), grid, dim3(kFusedThreads), 0, st, a, m);
-  else hipLaunchKernelGGL((k_fused<FORM, false, BC>), grid, dim3(kFusedThreads), 0, st, a, m);
+  if (moments) hipLaunchKernelGGL((k_fused<S, FORM, true, BC>), tile_grid<S>(a.g), dim3(S::NT), 0, st, a, m);
+  else hipLaunchKernelGGL((k_fused<S, FORM, false, BC>), tile_grid<S>(a.g), dim3(S::NT), 0, st, a, m);
   return hipGetLastError();
 }
 
+// Single lattices: every boundary set-up in shape 0; periodic lattices also
+// in the other shapes (step only; the moments run in shape 0).
 template <int FORM>
-hipError_t launch_form(const StepArgs& a, const MomentArgs& m, bool moments, hipStream_t st) {
-  switch (a.c.wall_x | (a.c.wall_y << 1)) {
-    case 0: return launch_fused_t<FORM, 0>(a, m, moments, st);
-    case 1: return launch_fused_t<FORM, 1>(a, m, moments, st);
-    case 2: return launch_fused_t<FORM, 2>(a, m, moments, st);
-    default: return launch_fused_t<FORM, 3>(a, m, moments, st);
+hipError_t launch_form(int shape, const StepArgs& a, const MomentArgs& m, bool moments, hipStream_t st) {
+  const int bc = a.c.wall_x | (a.c.wall_y << 1);
+  if (!moments && bc == 0) {
+    switch (shape) {
+      case 1: return launch_fused_t<S1, FORM, 0>(a, m, false, st);
+      case 2: return launch_fused_t<S2, FORM, 0>(a, m, false, st);
+      case 3: return launch_fused_t<S3, FORM, 0>(a, m, false, st);
+      default: break;
+    }
+  }
+  switch (bc) {
+    case 0: return launch_fused_t<S0, FORM, 0>(a, m, moments, st);
+    case 1: return launch_fused_t<S0, FORM, 1>(a, m, moments, st);
+    case 2: return launch_fused_t<S0, FORM, 2>(a, m, moments, st);
+    default: return launch_fused_t<S0, FORM, 3>(a, m, moments, st);
   }
 }
 
-hipError_t dispatch(int form, const StepArgs& a, const MomentArgs& m, bool moments, hipStream_t st) {
+hipError_t dispatch(int form, int shape, const StepArgs& a, const MomentArgs& m, bool moments, hipStream_t st) {
   switch (form) {
-    case 0: return launch_form<0>(a, m, moments, st);
-    case 1: return launch_form<1>(a, m, moments, st);
-    case 2: return launch_form<2>(a, m, moments, st);
-    case 3: return launch_form<3>(a, m, moments, st);
-    case 4: return launch_form<4>(a, m, moments, st);
-    case 5: return launch_form<5>(a, m, moments, st);
-    case 6: return launch_form<6>(a, m, moments, st);
-    case 7: return launch_form<7>(a, m, moments, st);
+    case 0: return launch_form<0>(shape, a, m, moments, st);
+    case 1: return launch_form<1>(shape, a, m, moments, st);
+    case 2: return launch_form<2>(shape, a, m, moments, st);
+    case 3: return launch_form<3>(shape, a, m, moments, st);
+    case 4: return launch_form<4>(shape, a, m, moments, st);
+    case 5: return launch_form<5>(shape, a, m, moments, st);
+    case 6: return launch_form<6>(shape, a, m, moments, st);
+    case 7: return launch_form<7>(shape, a, m, moments, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-}  // namespace
-
-hipError_t launch_fused(int form, const StepArgs& a, hipStream_t s) { return dispatch(form, a, MomentArgs{}, false, s); }
-
-hipError_t launch_moments(int form, const StepArgs& a, const MomentArgs& m, hipStream_t s) {
-  return dispatch(form, a, m, true, s);
-}
-
-hipError_t launch_phi(const float* snew, double* phi, const Grid& g, int wall_x, int wall_y, hipStream_t s) {
-  const int nb = ((g.nx + kTX - 1) / kTX) * ((g.ny + kTY - 1) / kTY);
-  dim3 grid((nb + kXcds - 1) / kXcds * kXcds);
-  switch (wall_x | (wall_y << 1)) {
-    case 0: hipLaunchKernelGGL(k_phi<0>, grid, dim3(kFusedThreads), 0, s, snew, phi, g); break;
-    case 1: hipLaunchKernelGGL(k_phi<1>, grid, dim3(kFusedThreads), 0, s, snew, phi, g); break;
-    case 2: hipLaunchKernelGGL(k_phi<2>, grid, dim3(kFusedThreads), 0, s, snew, phi, g); break;
-    default: hipLaunchKernelGGL(k_phi<3>, grid, dim3(kFusedThreads), 0, s, snew, phi, g); break;
+template <class S>
+hipError_t launch_phi_t(const float* snew, double* phi, const Grid& g, int bc, hipStream_t s) {
+  switch (bc) {
+    case 0: hipLaunchKernelGGL((k_phi<S, 0>), tile_grid<S>(g), dim3(S::NT), 0, s, snew, phi, g); break;
+    case 1: hipLaunchKernelGGL((k_phi<S, 1>), tile_grid<S>(g), dim3(S::NT), 0, s, snew, phi, g); break;
+    case 2: hipLaunchKernelGGL((k_phi<S, 2>), tile_grid<S>(g), dim3(S::NT), 0, s, snew, phi, g); break;
+    default: hipLaunchKernelGGL((k_phi<S, 3>), tile_grid<S>(g), dim3(S::NT), 0, s, snew, phi, g); break;
   }
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fused(int form, int shape, const StepArgs& a, hipStream_t s) {
+  return dispatch(form, shape, a, MomentArgs{}, false, s);
+}
+
+hipError_t launch_moments(int form, const StepArgs& a, const MomentArgs& m, hipStream_t s) {
+  return dispatch(form, 0, a, m, true, s);
+}
+
+hipError_t launch_phi(const float* snew, double* phi, const Grid& g, int wall_x, int wall_y, int shape, hipStream_t s) {
+  switch (shape) {
+    case 1: return launch_phi_t<S1>(snew, phi, g, wall_x | (wall_y << 1), s);
+    case 2: return launch_phi_t<S2>(snew, phi, g, wall_x | (wall_y << 1), s);
+    case 3: return launch_phi_t<S3>(snew, phi, g, wall_x | (wall_y << 1), s);
+    default: return launch_phi_t<S0>(snew, phi, g, wall_x | (wall_y << 1), s);
+  }
 }
 
 hipError_t launch_init(const float* phi0, const float* ux0, const float* uy0, float* s_tmp, float* s0, double* phi,
@@ -1165,45 +1223,66 @@ hipError_t launch_fill_int(int* p, int value, int n, hipStream_t s) {
 
 namespace pflbm {
 
-template <int FORM>
+template <class S, int FORM>
 void launch_batch_form(bool fast, dim3 grid, hipStream_t s, const BatchInst* inst, const TileRef* tiles, char* ws,
                        int t0, int t1, int parity) {
   if (fast)
-    hipLaunchKernelGGL((k_batch_fused<FORM, true>), grid, dim3(kFusedThreads), 0, s, inst, tiles, ws, t0, t1, parity);
+    hipLaunchKernelGGL((k_batch_fused<S, FORM, true>), grid, dim3(S::NT), 0, s, inst, tiles, ws, t0, t1, parity);
   else
-    hipLaunchKernelGGL((k_batch_fused<FORM, false>), grid, dim3(kFusedThreads), 0, s, inst, tiles, ws, t0, t1, parity);
+    hipLaunchKernelGGL((k_batch_fused<S, FORM, false>), grid, dim3(S::NT), 0, s, inst, tiles, ws, t0, t1, parity);
+}
+
+template <class S>
+void launch_batch_shape(int form, bool fast, dim3 grid, hipStream_t s, const BatchInst* inst, const TileRef* tiles,
+                        char* ws, int t0, int t1, int parity) {
+  switch (form) {
+    case 0: launch_batch_form<S, 0>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    case 1: launch_batch_form<S, 1>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    case 2: launch_batch_form<S, 2>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    case 3: launch_batch_form<S, 3>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    case 4: launch_batch_form<S, 4>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    case 5: launch_batch_form<S, 5>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    case 6: launch_batch_form<S, 6>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    case 7: launch_batch_form<S, 7>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    default: launch_batch_form<S, -1>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+  }
 }
 
 hipError_t launch_batch_fused(const BatchInst* inst, const TileRef* tiles, char* ws, int t0, int t1, int form,
-                              int fast, int parity, int nblocks, hipStream_t s) {
+                              int fast, int parity, int nblocks, int shape, hipStream_t s) {
   const dim3 grid(nblocks);
-  switch (form) {
-    case 0: launch_batch_form<0>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
-    case 1: launch_batch_form<1>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
-    case 2: launch_batch_form<2>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
-    case 3: launch_batch_form<3>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
-    case 4: launch_batch_form<4>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
-    case 5: launch_batch_form<5>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
-    case 6: launch_batch_form<6>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
-    case 7: launch_batch_form<7>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
-    default: launch_batch_form<-1>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+  switch (shape) {
+    case 1: launch_batch_shape<S1>(form, fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    case 2: launch_batch_shape<S2>(form, fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    case 3: launch_batch_shape<S3>(form, fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    default: launch_batch_shape<S0>(form, fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_batch_phi(const BatchInst* inst, const TileRef* tiles, char* ws, int ntiles, int parity, int nblocks,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_phi, dim3(nblocks), dim3(kFusedThreads), 0, s, inst, tiles, ws, ntiles, parity);
+                            int shape, hipStream_t s) {
+  switch (shape) {
+    case 1: hipLaunchKernelGGL(k_batch_phi<S1>, dim3(nblocks), dim3(S1::NT), 0, s, inst, tiles, ws, ntiles, parity); break;
+    case 2: hipLaunchKernelGGL(k_batch_phi<S2>, dim3(nblocks), dim3(S2::NT), 0, s, inst, tiles, ws, ntiles, parity); break;
+    case 3: hipLaunchKernelGGL(k_batch_phi<S3>, dim3(nblocks), dim3(S3::NT), 0, s, inst, tiles, ws, ntiles, parity); break;
+    default: hipLaunchKernelGGL(k_batch_phi<S0>, dim3(nblocks), dim3(S0::NT), 0, s, inst, tiles, ws, ntiles, parity); break;
+  }
   return hipGetLastError();
 }
 
-// Resident workgroups per CU of the batched step kernel (the any-form
-// kernel with the interior path, the largest register footprint).
-int fused_blocks_per_cu() {
+// Resident workgroups per CU of the batched step kernel of a tile shape (the
+// any-form kernel with the interior path, the largest register footprint).
+int fused_blocks_per_cu(int shape) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_fused<-1, true>, kFusedThreads, 0) != hipSuccess || n < 1)
-    n = 1;
-  return n;
+  hipError_t e;
+  switch (shape) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_fused<S1, -1, true>, S1::NT, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_fused<S2, -1, true>, S2::NT, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_fused<S3, -1, true>, S3::NT, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_fused<S0, -1, true>, S0::NT, 0); break;
+  }
+  return (e != hipSuccess || n < 1) ? 1 : n;
 }
 
 }  // namespace pflbm

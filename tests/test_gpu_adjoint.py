@@ -217,3 +217,56 @@ def test_adjoint_refuses_free_slip_walls():
     with pytest.raises(LbmError) as e:
         P.Adjoint(sim)
     assert "free-slip" in str(e.value) or "no-slip" in str(e.value)
+
+
+def test_rollout_forward_is_one_forward_and_backward_runs_the_adjoint():
+    """rollout() under torch.no_grad costs about one plain forward run (no
+    checkpoints, no adjoint); with gradients, forward keeps only the
+    checkpoints and backward() runs the adjoint.  L and the gradients equal
+    those of adjoint_gradients() bit for bit."""
+    import time
+
+    import paper_2012_14729_amd as P
+    p, phi0, ux0, uy0 = WL.config_shear(nx=128, ny=64, R=16.0, Re=1.0, Ca=0.2)
+    T, form = 400, "stf2"
+    dev = torch.device("cuda")
+    f32 = lambda a: torch.tensor(np.asarray(a, np.float32), device=dev)   # noqa: E731
+    phi0_t, ux, uy = f32(phi0), f32(ux0), f32(uy0)
+    s = P.Simulation(dict(p.as_dict(), sigma=1.1 * p.sigma), phi0_t, ux, uy, device=dev)
+    s.step(T, form)
+    target = s.moments(form)["phi"]
+    del s
+    loss_ref, dphi_ref, ds_ref, dm_ref = P.adjoint_gradients(p.as_dict(), form, T, phi0_t, target, ux, uy)
+
+    def plain():
+        sim = P.Simulation(p.as_dict(), phi0_t, ux, uy, device=dev)
+        sim.step(T, form)
+        return sim.moments(form)["phi"]
+
+    def nograd():
+        with torch.no_grad():
+            return P.rollout(phi0_t, p.sigma, p.M, p.as_dict(), form, T, target, ux, uy)
+
+    plain(), nograd()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    L0 = nograd()
+    torch.cuda.synchronize()
+    t_nograd = time.perf_counter() - t0
+    print(f"[rollout split] plain forward {t_plain * 1e3:.1f} ms, L under no_grad {t_nograd * 1e3:.1f} ms", flush=True)
+    assert float(L0) == loss_ref
+    assert t_nograd < 2.0 * t_plain + 0.02
+
+    ph = phi0_t.clone().requires_grad_(True)
+    sg = torch.tensor(p.sigma, dtype=torch.float64, requires_grad=True)
+    mm = torch.tensor(p.M, dtype=torch.float64, requires_grad=True)
+    L = P.rollout(ph, sg, mm, p.as_dict(), form, T, target, ux, uy)
+    assert float(L) == loss_ref
+    assert ph.grad is None
+    L.backward()
+    assert float(sg.grad) == ds_ref and float(mm.grad) == dm_ref
+    assert torch.equal(ph.grad, dphi_ref.to(torch.float32))

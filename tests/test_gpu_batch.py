@@ -125,3 +125,25 @@ def test_tuned_batch_starts_from_phi0(monkeypatch):
         mt, mp = tuned.moments(k), plain.moments(k)
         for key in ("phi", "rho", "ux", "uy", "P"):
             assert torch.equal(mt[key], mp[key]), (k, key)
+
+
+@pytest.mark.parametrize("shape", [0, 1, 2, 3])
+@pytest.mark.parametrize("cfg", ["1,1,2", "0,1,0"])
+def test_every_tile_shape_matches_single_lattice(shape, cfg, monkeypatch):
+    """Batched step kernels in every tile shape (PFLBM_BATCH_SHAPE) evolve
+    the instances bit for bit as single lattices."""
+    import paper_2012_14729_amd as P
+    params, forms, phis = wide_batch()
+    monkeypatch.setenv("PFLBM_BATCH_CFG", cfg)
+    monkeypatch.setenv("PFLBM_BATCH_SHAPE", str(shape))
+    b = P.Batch([p.as_dict() for p in params], forms, phis)
+    monkeypatch.delenv("PFLBM_BATCH_SHAPE", raising=False)
+    b.step(19)
+    torch.cuda.synchronize()
+    assert not any(b.status())
+    for k, (p, f, phi) in enumerate(zip(params, forms, phis)):
+        s = P.Simulation(p.as_dict(), phi)
+        s.step(19, P.FORMS[f])
+        ms, mb = s.moments(P.FORMS[f]), b.moments(k)
+        for key in ("phi", "rho", "ux", "uy", "P"):
+            assert torch.equal(ms[key], mb[key]), (shape, cfg, k, key)

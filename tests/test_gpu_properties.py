@@ -167,3 +167,36 @@ def test_interior_fast_path_bitwise_equals_general_path(case, monkeypatch):
     nd = int((a != b).sum())
     print(f"[fast-vs-general] {case}: {nd} differing bytes of {a.size}", flush=True)
     assert nd == 0
+
+
+@pytest.mark.parametrize("shape", [1, 2, 3])
+@pytest.mark.parametrize("case", ["periodic_cpf1", "ragged_csf2"])
+def test_every_tile_shape_is_bitwise_equal(shape, case, monkeypatch):
+    """The step kernels run in any of the tile shapes 64x8 (0), 32x16 (1),
+    32x8 (2), 64x4 (3); PFLBM_TILE selects one for a periodic lattice.  A
+    node's velocity is the same arithmetic whether its own tile or a
+    neighbouring tile's ring evaluates it, so every shape must give the same
+    state bit for bit (ragged case: 200 = 6 x 32 + 8 = 3 x 64 + 8 columns,
+    150 rows)."""
+    import paper_2012_14729_amd as P
+    if case == "periodic_cpf1":
+        nx, ny, form = 320, 96, "cpf1"
+        p = WL.ParamSet(nx=nx, ny=ny, rho1=10.0, rho2=1.0, nu1=0.1, nu2=0.2, sigma=5e-3, W=4.0, M=0.1, tau_h=0.8)
+        phi0 = WL.two_droplets(nx, ny, 20.0, 14.0, 2.0, 4.0)
+    else:
+        nx, ny, form = 200, 150, "csf2"
+        p = WL.ParamSet(nx=nx, ny=ny, rho1=100.0, rho2=1.0, nu1=0.1, nu2=0.1, sigma=2e-3, W=4.0, M=0.1, tau_h=0.8)
+        phi0 = WL.two_droplets(nx, ny, 30.0, 22.0, 2.0, 4.0)
+    phi0 = np.asarray(phi0, np.float32)
+    blobs = []
+    for sh in (0, shape):
+        monkeypatch.setenv("PFLBM_TILE", str(sh))
+        sim = P.Simulation(p.as_dict(), phi0)
+        sim.step(30, form)
+        blobs.append(sim.save().cpu())
+        assert not sim.status()
+    monkeypatch.delenv("PFLBM_TILE", raising=False)
+    a, b = blobs[0].numpy(), blobs[1].numpy()
+    nd = int((a != b).sum())
+    print(f"[tile shape] {case} shape {shape}: {nd} differing bytes of {a.size}", flush=True)
+    assert nd == 0
