@@ -201,9 +201,10 @@ int lbm_batch_destroy(lbm_batch* batch);
  * pre-collision state s = (f_0..f_8, h_0..h_8, J_x, J_y) of every node: 20
  * FP64 planes of nx*ny values, row-major (x fastest), plane order f, h, J.
  * An lbm_adj is bound to one simulation and differentiates its current
- * state; it keeps per-node accumulators of dL/dsigma and dL/dM.
- * The workspace (FP64 scratch for the recomputed step and its adjoint) is
- * caller-owned, 256-byte aligned, lbm_adjoint_workspace_bytes long.
+ * state (or a saved one); it keeps accumulators of dL/dsigma and dL/dM.
+ * The workspace (FP64 scratch of one adjoint step, the accumulators and the
+ * buffers of lbm_adjoint_init) is caller-owned, 256-byte aligned,
+ * lbm_adjoint_workspace_bytes long.
  * ------------------------------------------------------------------------ */
 typedef struct lbm_adj lbm_adj;
 int lbm_adjoint_workspace_bytes(const lbm_params* p, size_t* bytes);
@@ -219,17 +220,20 @@ int lbm_adjoint_reset(lbm_adj* adj, void* stream);
 int lbm_adjoint_seed_phi_misfit(lbm_adj* adj, const float* d_target, double* d_lambda, double* h_loss,
                                 void* stream);
 /* One step backwards: the simulation must hold the forward state s_t of the
- * step being differentiated (restore it first).  In: lambda_{t+1}; out
- * (in place): lambda_t = (ds_{t+1}/ds_t)^T lambda_{t+1}.  Adds this step's
- * contributions to dL/dsigma and dL/dM (Eqs. 6, 29-37, 41-43). */
-int lbm_adjoint_step(lbm_adj* adj, int32_t force_form, double* d_lambda, void* stream);
+ * step being differentiated (restore it first).  In: d_lambda_in =
+ * lambda_{t+1}; out: d_lambda_out = lambda_t = (ds_{t+1}/ds_t)^T lambda_{t+1}
+ * (Eqs. 6, 29-37, 41-43 transposed).  The two arrays must not overlap
+ * (LBM_E_INVAL).  Adds this step's contributions to dL/dsigma and dL/dM. */
+int lbm_adjoint_step(lbm_adj* adj, int32_t force_form, const double* d_lambda_in, double* d_lambda_out,
+                     void* stream);
 /* The same step linearised about the state held in d_blob (written by
  * lbm_save of this adjoint's simulation) instead of the simulation's current
  * state; the simulation is not touched. */
-int lbm_adjoint_step_blob(lbm_adj* adj, const void* d_blob, int32_t force_form, double* d_lambda, void* stream);
+int lbm_adjoint_step_blob(lbm_adj* adj, const void* d_blob, int32_t force_form, const double* d_lambda_in,
+                          double* d_lambda_out, void* stream);
 /* Adjoint of lbm_init (reading A11): dL/dphi0 (nx*ny FP64) from lambda_0,
- * adding the initial state's contributions to dL/dsigma and dL/dM.  phi0,
- * u0 as given to lbm_init. */
+ * and the initial state's contributions to dL/dsigma and dL/dM (replacing
+ * those of an earlier call).  phi0, u0 as given to lbm_init. */
 int lbm_adjoint_init(lbm_adj* adj, const float* d_phi0, const float* d_ux0, const float* d_uy0,
                      const double* d_lambda0, double* d_dphi0, void* stream);
 /* Synchronises; returns the accumulated dL/dsigma and dL/dM. */

@@ -238,20 +238,33 @@ class Adjoint:
         check(lib().lbm_adjoint_seed_phi_misfit(self._h, _ptr(t), _ptr(lam), C.byref(loss), _stream(stream)))
         return lam, loss.value
 
-    def step(self, lam, form, stream=None):
-        check_lambda(lam, self.sim.ny, self.sim.nx, self.workspace.device)
-        check(lib().lbm_adjoint_step(self._h, form_index(form), _ptr(lam), _stream(stream)))
-        return lam
+    def _out(self, lam, out):
+        if out is None:
+            out = torch.empty_like(lam)
+        check_lambda(out, self.sim.ny, self.sim.nx, self.workspace.device)
+        if out.data_ptr() == lam.data_ptr():
+            raise ValueError("the adjoint step writes lambda_n to a second array, not in place")
+        return out
 
-    def step_blob(self, blob, lam, form, stream=None):
+    def step(self, lam, form, out=None, stream=None):
+        """lambda_n from lambda_{n+1} = lam about the simulation's current
+        state; written to `out` (a new tensor if None), which is returned."""
+        check_lambda(lam, self.sim.ny, self.sim.nx, self.workspace.device)
+        out = self._out(lam, out)
+        check(lib().lbm_adjoint_step(self._h, form_index(form), _ptr(lam), _ptr(out), _stream(stream)))
+        return out
+
+    def step_blob(self, blob, lam, form, out=None, stream=None):
         """Adjoint step about the state in `blob` (a Simulation.save() of this
-        adjoint's simulation)."""
+        adjoint's simulation); lambda_n goes to `out` (new if None)."""
         check_lambda(lam, self.sim.ny, self.sim.nx, self.workspace.device)
         if not (torch.is_tensor(blob) and blob.dtype == torch.uint8 and blob.numel() == self.sim.state_bytes()
                 and blob.device == self.workspace.device):
             raise ValueError("blob must be a uint8 tensor from Simulation.save() on the same device")
-        check(lib().lbm_adjoint_step_blob(self._h, _ptr(blob), form_index(form), _ptr(lam), _stream(stream)))
-        return lam
+        out = self._out(lam, out)
+        check(lib().lbm_adjoint_step_blob(self._h, _ptr(blob), form_index(form), _ptr(lam), _ptr(out),
+                                          _stream(stream)))
+        return out
 
     def init(self, lam, phi0, ux0=None, uy0=None, stream=None):
         dev = self.workspace.device
@@ -324,6 +337,7 @@ class _Checkpointed:
         if self.lam is None or (self.T > 0 and not self.ckpt):
             raise RuntimeError("backward needs a forward pass that kept its checkpoints")
         sim, adj, lam, every = self.sim, self.adj, self.lam, self.every
+        spare = torch.empty_like(lam)   # lambda ping-pongs between two arrays
         pool = [torch.empty_like(self.ckpt[0]) for _ in range(min(every, self.T))] if self.ckpt else []
         L = lib()
         for s in reversed(range(len(self.ckpt))):
@@ -334,7 +348,8 @@ class _Checkpointed:
                 if t < t_hi - 1:
                     sim.step(1, self.form)
             for t in reversed(range(t_lo, t_hi)):
-                adj.step_blob(pool[t - t_lo], lam, self.form)
+                adj.step_blob(pool[t - t_lo], lam, self.form, out=spare)
+                lam, spare = spare, lam
             self.ckpt[s] = None   # this checkpoint is no longer needed
         del pool
         self.ckpt = []

@@ -42,16 +42,19 @@ def sources():
 
 def build(verbose: bool = False) -> str:
     cc = hipcc()
-    objs = []
     with tempfile.TemporaryDirectory(prefix="pflbm_build_") as tmp:
-        for src in sources():
+        jobs = []
+        for src in sources():   # one hipcc per source, in parallel
             obj = os.path.join(tmp, os.path.basename(src) + ".o")
             cmd = [cc, *HIPCC_FLAGS, "-c", src, "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
-            r = subprocess.run(cmd, capture_output=True, text=True)
-            if r.returncode != 0:
-                raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
+            jobs.append((src, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
+        objs = []
+        for src, obj, proc in jobs:
+            _, err = proc.communicate()
+            if proc.returncode != 0:
+                raise RuntimeError(f"hipcc failed on {src}:\n{err}")
             objs.append(obj)
         out_tmp = LIB + ".tmp"
         cmd = [cc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", out_tmp]

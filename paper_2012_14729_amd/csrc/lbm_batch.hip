@@ -1,4 +1,5 @@
-// C-ABI host code of the batched engine (declarations in include/lbm.h).
+// Batched engine: its device kernels (persistent walks over a tile list of
+// every instance) and the C-ABI host code (declarations in include/lbm.h).
 //
 // `count` independent periodic lattices share one caller-provided workspace:
 //   [instance descriptors][tile list][status ints][rho0 sums][partial sums]
@@ -30,8 +31,166 @@
 #include <vector>
 
 #include "../../include/lbm.h"
-#include "lbm_internal.hpp"
+#include "lbm_tile.hpp"
 
+// ---------------------------------------------------------------------------
+// Device side: the batched step kernels over the tile list.
+// ---------------------------------------------------------------------------
+namespace pflbm {
+
+namespace {
+
+// Batched step: persistent workgroups walk a tile list covering every
+// instance (sorted by force form, then instance).  A launch covers the tile
+// range [t0, t1), cut into 8 contiguous bands, one per XCD; the workgroups of
+// an XCD stride through its band, so consecutive tiles of an instance share
+// that XCD's L2.
+__device__ __forceinline__ void band(int t0, int t1, int& first, int& end, int& stride) {
+  const int per = (t1 - t0 + kXcds - 1) / kXcds;
+  const int beg = t0 + (int)(blockIdx.x % kXcds) * per;
+  end = min(t1, beg + per);
+  first = beg + (int)(blockIdx.x / kXcds);
+  stride = (int)(gridDim.x / kXcds);
+}
+
+// One tile of instance descriptor bi: FAST_OK lets interior tiles take the
+// interior addressing path (more registers); otherwise every tile takes the
+// general one.
+template <class S, int FORM, bool FAST_OK>
+__device__ __forceinline__ void batch_tile(Lds<S>& s, const StepArgs& a, int tx, int ty) {
+  if constexpr (FAST_OK) fused_tile<S, FORM, false, 0, true>(s, a, MomentArgs{}, tx, ty);
+  else tile_impl<S, FORM, false, 0, false, true>(s, a, MomentArgs{}, tx, ty);
+}
+
+// Step arguments of a batch instance with its pointers rebuilt from the
+// workspace base, a kernel argument: pointers read from the descriptor would
+// be generic, and every access through them a flat one (which also counts
+// against the LDS wait counter).
+__device__ __forceinline__ StepArgs batch_args(const BatchInst& bi, int parity, char* ws) {
+  StepArgs a = bi.a[parity];
+  a.sin = (const float*)(ws + bi.off_s[parity]);
+  a.sout = (float*)(ws + bi.off_s[1 - parity]);
+  a.phi = (const double*)(ws + bi.off_phi);
+  a.status = (int*)(ws + bi.off_status);
+  return a;
+}
+
+// FORM >= 0: every tile of [t0, t1) has that force form (the tile list is
+// sorted by form); FORM < 0: any form, dispatched per tile.
+template <class S, int FORM, bool FAST_OK>
+__global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_fused(
+    const BatchInst* __restrict__ inst, const TileRef* __restrict__ tiles, char* ws, int t0, int t1, int parity) {
+  __shared__ Lds<S> s;
+  int first, end, stride;
+  band(t0, t1, first, end, stride);
+  for (int t = first; t < end; t += stride) {
+    const TileRef tr = tiles[t];
+    const BatchInst& bi = inst[tr.inst];
+    __syncthreads();   // the previous tile is done with the LDS
+    const StepArgs a = batch_args(bi, parity, ws);
+    if constexpr (FORM >= 0) {
+      batch_tile<S, FORM, FAST_OK>(s, a, tr.tx, tr.ty);
+    } else {
+      switch (bi.form) {
+        case 0: batch_tile<S, 0, FAST_OK>(s, a, tr.tx, tr.ty); break;
+        case 1: batch_tile<S, 1, FAST_OK>(s, a, tr.tx, tr.ty); break;
+        case 2: batch_tile<S, 2, FAST_OK>(s, a, tr.tx, tr.ty); break;
+        case 3: batch_tile<S, 3, FAST_OK>(s, a, tr.tx, tr.ty); break;
+        case 4: batch_tile<S, 4, FAST_OK>(s, a, tr.tx, tr.ty); break;
+        case 5: batch_tile<S, 5, FAST_OK>(s, a, tr.tx, tr.ty); break;
+        case 6: batch_tile<S, 6, FAST_OK>(s, a, tr.tx, tr.ty); break;
+        default: batch_tile<S, 7, FAST_OK>(s, a, tr.tx, tr.ty); break;
+      }
+    }
+  }
+}
+
+template <class S>
+__global__ __launch_bounds__(S::NT) void k_batch_phi(const BatchInst* __restrict__ inst,
+                                                     const TileRef* __restrict__ tiles, char* ws, int ntiles,
+                                                     int parity) {
+  int first, end, stride;
+  band(0, ntiles, first, end, stride);
+  for (int t = first; t < end; t += stride) {
+    const TileRef tr = tiles[t];
+    const StepArgs a = batch_args(inst[tr.inst], parity, ws);
+    phi_tile<S, 0>(a.sout, const_cast<double*>(a.phi), a.g, tr.tx, tr.ty);
+  }
+}
+
+}  // namespace
+
+}  // namespace pflbm
+
+namespace pflbm {
+
+template <class S, int FORM>
+void launch_batch_form(bool fast, dim3 grid, hipStream_t s, const BatchInst* inst, const TileRef* tiles, char* ws,
+                       int t0, int t1, int parity) {
+  if (fast)
+    hipLaunchKernelGGL((k_batch_fused<S, FORM, true>), grid, dim3(S::NT), 0, s, inst, tiles, ws, t0, t1, parity);
+  else
+    hipLaunchKernelGGL((k_batch_fused<S, FORM, false>), grid, dim3(S::NT), 0, s, inst, tiles, ws, t0, t1, parity);
+}
+
+template <class S>
+void launch_batch_shape(int form, bool fast, dim3 grid, hipStream_t s, const BatchInst* inst, const TileRef* tiles,
+                        char* ws, int t0, int t1, int parity) {
+  switch (form) {
+    case 0: launch_batch_form<S, 0>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    case 1: launch_batch_form<S, 1>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    case 2: launch_batch_form<S, 2>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    case 3: launch_batch_form<S, 3>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    case 4: launch_batch_form<S, 4>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    case 5: launch_batch_form<S, 5>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    case 6: launch_batch_form<S, 6>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    case 7: launch_batch_form<S, 7>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    default: launch_batch_form<S, -1>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+  }
+}
+
+hipError_t launch_batch_fused(const BatchInst* inst, const TileRef* tiles, char* ws, int t0, int t1, int form,
+                              int fast, int parity, int nblocks, int shape, hipStream_t s) {
+  const dim3 grid(nblocks);
+  switch (shape) {
+    case 1: launch_batch_shape<S1>(form, fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    case 2: launch_batch_shape<S2>(form, fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    case 3: launch_batch_shape<S3>(form, fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    default: launch_batch_shape<S0>(form, fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_phi(const BatchInst* inst, const TileRef* tiles, char* ws, int ntiles, int parity, int nblocks,
+                            int shape, hipStream_t s) {
+  switch (shape) {
+    case 1: hipLaunchKernelGGL(k_batch_phi<S1>, dim3(nblocks), dim3(S1::NT), 0, s, inst, tiles, ws, ntiles, parity); break;
+    case 2: hipLaunchKernelGGL(k_batch_phi<S2>, dim3(nblocks), dim3(S2::NT), 0, s, inst, tiles, ws, ntiles, parity); break;
+    case 3: hipLaunchKernelGGL(k_batch_phi<S3>, dim3(nblocks), dim3(S3::NT), 0, s, inst, tiles, ws, ntiles, parity); break;
+    default: hipLaunchKernelGGL(k_batch_phi<S0>, dim3(nblocks), dim3(S0::NT), 0, s, inst, tiles, ws, ntiles, parity); break;
+  }
+  return hipGetLastError();
+}
+
+// Resident workgroups per CU of the batched step kernel of a tile shape (the
+// any-form kernel with the interior path, the largest register footprint).
+int fused_blocks_per_cu(int shape) {
+  int n = 0;
+  hipError_t e;
+  switch (shape) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_fused<S1, -1, true>, S1::NT, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_fused<S2, -1, true>, S2::NT, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_fused<S3, -1, true>, S3::NT, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_fused<S0, -1, true>, S0::NT, 0); break;
+  }
+  return (e != hipSuccess || n < 1) ? 1 : n;
+}
+
+}  // namespace pflbm
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
 using namespace pflbm;
 
 namespace {

@@ -139,6 +139,7 @@ hipError_t launch_moments(int form, const StepArgs& a, const MomentArgs& m, hipS
 hipError_t launch_phi(const float* snew, double* phi, const Grid& g, int wall_x, int wall_y, int shape, hipStream_t s);
 hipError_t launch_init(const float* phi0, const float* ux0, const float* uy0, float* s_tmp, float* s0, double* phi,
                        const Grid& g, const Phys& c, hipStream_t s);
+// sum of the phi plane: at most npartial (and one per 256 nodes) partial sums, then one
 hipError_t launch_phi_sum(const double* phi, const Grid& g, double* partial, int npartial, double* out,
                           hipStream_t s);
 hipError_t launch_fill_int(int* p, int value, int n, hipStream_t s);

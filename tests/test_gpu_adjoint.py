@@ -82,8 +82,7 @@ def test_one_adjoint_step_matches_oracle_vjp(case, form):
     sim = P.Simulation(p.as_dict(), np.asarray(phi0, np.float32), ux0, uy0)
     sim.step(k, form)
     adj = P.Adjoint(sim)
-    lam = lam1.to("cuda")
-    adj.step(lam, form)
+    lam = adj.step(lam1.to("cuda"), form)
     got = lam.cpu().numpy()
     ds, dm = adj.param_grads()
     err = np.abs(got - ref).max() / np.abs(ref).max()
