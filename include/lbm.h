@@ -149,6 +149,16 @@ int lbm_state_bytes(const lbm_sim* sim, size_t* bytes);
 int lbm_save(lbm_sim* sim, void* d_blob, void* stream);
 int lbm_restore(lbm_sim* sim, const void* d_blob, void* stream);
 
+/* One time step (as lbm_step, same force form rules) from the state held in
+ * d_blob_in to d_blob_out, both in the lbm_save layout of this simulation;
+ * the simulation's own state and step counter are not touched.  The blobs
+ * must not overlap (LBM_E_INVAL).  d_blob_out's divergence flag is
+ * d_blob_in's plus this step's; its padding (lanes past nx of each row's last
+ * 64-node segment) is not written, so a zeroed output blob keeps equal
+ * states in equal blobs.  Used to recompute the states of a checkpoint
+ * segment without copies. */
+int lbm_step_blobs(lbm_sim* sim, const void* d_blob_in, void* d_blob_out, int32_t force_form, void* stream);
+
 /* Kernel timing with HIP events recorded on the launch stream around the
  * launches of one kernel.  period: 0 = off; k >= 1 = time the two launches of
  * every k-th step (step counter divisible by k), so k > 1 samples the launch

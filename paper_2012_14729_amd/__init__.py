@@ -136,6 +136,17 @@ class Simulation:
     def restore(self, blob, stream=None):
         check(lib().lbm_restore(self._h, _ptr(blob), _stream(stream)))
 
+    def step_blobs(self, blob_in, blob_out, form, stream=None):
+        """One step from the state in blob_in into blob_out (lbm_step_blobs);
+        the simulation itself is not touched."""
+        n = self.state_bytes()
+        for b in (blob_in, blob_out):
+            if not (torch.is_tensor(b) and b.dtype == torch.uint8 and b.numel() == n
+                    and b.device == self.workspace.device):
+                raise ValueError("blobs must be uint8 tensors from Simulation.save() on the same device")
+        check(lib().lbm_step_blobs(self._h, _ptr(blob_in), _ptr(blob_out), form_index(form), _stream(stream)))
+        return blob_out
+
     def set_timing(self, enable=True, period=1):
         """Time the kernels of every `period`-th step (lbm_set_timing); off if not enable."""
         check(lib().lbm_set_timing(self._h, int(period) if enable else 0))
@@ -305,11 +316,11 @@ class _Checkpointed:
 
     forward(): T steps from phi0, keeping (T / every) checkpoints; seeds
     lambda_T and computes L (lbm_adjoint_seed_phi_misfit).
-    backward(): per segment in reverse, restore its checkpoint, recompute
-    the segment's per-step states into a pool of `every` state blobs
-    (allocated once and reused by every segment), run the adjoint steps
-    backwards over them; then the adjoint of the initialisation.  Memory:
-    (T / every + every) states."""
+    backward(): per segment in reverse, recompute the segment's per-step
+    states from its checkpoint blob to blob (lbm_step_blobs, no copies) into
+    a pool of `every - 1` state blobs (allocated once, reused by every
+    segment), run the adjoint steps backwards over them; then the adjoint of
+    the initialisation.  Memory: (T / every + every) states."""
 
     def __init__(self, params, form, T, phi0, target, ux0=None, uy0=None, every=None):
         self.form, self.T = form, int(T)
@@ -338,17 +349,15 @@ class _Checkpointed:
             raise RuntimeError("backward needs a forward pass that kept its checkpoints")
         sim, adj, lam, every = self.sim, self.adj, self.lam, self.every
         spare = torch.empty_like(lam)   # lambda ping-pongs between two arrays
-        pool = [torch.empty_like(self.ckpt[0]) for _ in range(min(every, self.T))] if self.ckpt else []
-        L = lib()
+        npool = min(every, self.T) - 1
+        pool = [torch.zeros_like(self.ckpt[0]) for _ in range(npool)] if self.ckpt else []
         for s in reversed(range(len(self.ckpt))):
             t_lo, t_hi = s * every, min(self.T, (s + 1) * every)
-            sim.restore(self.ckpt[s])
-            for t in range(t_lo, t_hi):
-                check(L.lbm_save(sim._h, _ptr(pool[t - t_lo]), _stream(None)))
-                if t < t_hi - 1:
-                    sim.step(1, self.form)
+            states = [self.ckpt[s]] + pool[:t_hi - t_lo - 1]
+            for j in range(1, t_hi - t_lo):
+                sim.step_blobs(states[j - 1], states[j], self.form)
             for t in reversed(range(t_lo, t_hi)):
-                adj.step_blob(pool[t - t_lo], lam, self.form, out=spare)
+                adj.step_blob(states[t - t_lo], lam, self.form, out=spare)
                 lam, spare = spare, lam
             self.ckpt[s] = None   # this checkpoint is no longer needed
         del pool

@@ -51,6 +51,7 @@ _SIGS = {
     "lbm_state_bytes": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "lbm_save": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lbm_restore": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lbm_step_blobs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "lbm_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
     "lbm_kernel_time": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "lbm_destroy": (C.c_int, [C.c_void_p]),

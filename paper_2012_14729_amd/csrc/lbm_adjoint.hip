@@ -754,11 +754,12 @@ __global__ __launch_bounds__(kB) void k_adj_zero(double* p, long long n) {
   if (k < n) p[k] = 0.0;
 }
 
-// Deterministic two-level sum: kRed partial sums (grid-stride), then one block.
+// Deterministic two-level sum: one partial sum per block (grid-stride over
+// gridDim.x blocks), then one block sums the partials.
 __global__ __launch_bounds__(kB) void k_sum_part(const double* __restrict__ a, long long n, double* __restrict__ part) {
   __shared__ double red[kB];
   double s = 0.0;
-  for (long long k = (long long)blockIdx.x * kB + threadIdx.x; k < n; k += (long long)kRed * kB) s += a[k];
+  for (long long k = (long long)blockIdx.x * kB + threadIdx.x; k < n; k += (long long)gridDim.x * kB) s += a[k];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = kB / 2; w > 0; w >>= 1) {
@@ -768,10 +769,10 @@ __global__ __launch_bounds__(kB) void k_sum_part(const double* __restrict__ a, l
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-__global__ __launch_bounds__(kB) void k_sum_fin(const double* __restrict__ part, double* out) {
+__global__ __launch_bounds__(kB) void k_sum_fin(const double* __restrict__ part, int npart, double* out) {
   __shared__ double red[kB];
   double s = 0.0;
-  for (int k = threadIdx.x; k < kRed; k += kB) s += part[k];
+  for (int k = threadIdx.x; k < npart; k += kB) s += part[k];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = kB / 2; w > 0; w >>= 1) {
@@ -875,8 +876,10 @@ size_t adj_doubles(const lbm_params* p) {
 }
 
 int adj_sum(const double* a, long long n, double* part, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_sum_part, dim3(kRed), dim3(kB), 0, st, a, n, part);
-  hipLaunchKernelGGL(k_sum_fin, dim3(1), dim3(kB), 0, st, part, out);
+  const long long nb = (n + kB - 1) / kB;
+  const int np = nb < 1 ? 1 : (nb < kRed ? (int)nb : kRed);   // at most kRed partial sums
+  hipLaunchKernelGGL(k_sum_part, dim3(np), dim3(kB), 0, st, a, n, part);
+  hipLaunchKernelGGL(k_sum_fin, dim3(1), dim3(kB), 0, st, part, np, out);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? LBM_OK : set_error(LBM_E_HIP, "adjoint sum: %s", hipGetErrorString(e));
 }

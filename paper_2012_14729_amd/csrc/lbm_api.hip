@@ -325,7 +325,7 @@ int lbm_step(lbm_sim* s, int32_t nsteps, int32_t form, void* stream) {
       if (int r = timer_stop(s, 0, slot, st)) return r;
       if (int r = timer_start(s, 1, st, &slot)) return r;
     }
-    HIPCHK(launch_phi(a.sout, s->phi(), s->L.g, s->c.wall_x, s->c.wall_y, s->shape, st));
+    HIPCHK(launch_phi(a.sout, s->phi(), s->phi(), s->L.g, s->c.wall_x, s->c.wall_y, s->shape, st));
     if (timed)
       if (int r = timer_stop(s, 1, slot, st)) return r;
     s->cur = 1 - s->cur;
@@ -393,6 +393,31 @@ int lbm_restore(lbm_sim* s, const void* d_blob, void* stream) {
   void* dst[3] = {s->S(s->cur), s->phi(), s->status()};
   const size_t bytes[3] = {sb, pb, sizeof(int)};
   HIPCHK(launch_copies(src, dst, bytes, 3, nullptr, 0, (hipStream_t)stream));
+  return LBM_OK;
+}
+
+int lbm_step_blobs(lbm_sim* s, const void* d_blob_in, void* d_blob_out, int32_t form, void* stream) {
+  if (!s || !d_blob_in || !d_blob_out) return fail(LBM_E_INVAL, "NULL argument");
+  if (form < 0 || form >= LBM_NUM_FORMS) return fail(LBM_E_INVAL, "bad force form %d", form);
+  const size_t sb = s->state_floats() * sizeof(float), pb = (size_t)s->L.g.ps * sizeof(double);
+  const size_t tot = sb + pb + kAlign;
+  const char* bi = (const char*)d_blob_in;
+  char* bo = (char*)d_blob_out;
+  if (bi < bo + tot && bo < bi + tot) return fail(LBM_E_INVAL, "the two blobs must not overlap");
+  hipStream_t st = (hipStream_t)stream;
+  // the divergence flag carries over (the kernels then add to it), the tail is zero
+  const void* src[1] = {bi + sb + pb};
+  void* dst[1] = {bo + sb + pb};
+  const size_t bytes[1] = {sizeof(int)};
+  HIPCHK(launch_copies(src, dst, bytes, 1, bo + sb + pb + sizeof(int), kAlign - sizeof(int), st));
+  StepArgs a = step_args(s);
+  a.sin = (const float*)bi;
+  a.sout = (float*)bo;
+  a.phi = (const double*)(bi + sb);
+  a.status = (int*)(bo + sb + pb);
+  HIPCHK(launch_fused(form, s->shape, a, st));
+  HIPCHK(launch_phi(a.sout, (const double*)(bi + sb), (double*)(bo + sb), s->L.g, s->c.wall_x, s->c.wall_y, s->shape,
+                    st));
   return LBM_OK;
 }
 

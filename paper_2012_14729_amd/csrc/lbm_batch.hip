@@ -114,7 +114,7 @@ __global__ __launch_bounds__(S::NT) void k_batch_phi(const BatchInst* __restrict
   for (int t = first; t < end; t += stride) {
     const TileRef tr = tiles[t];
     const StepArgs a = batch_args(inst[tr.inst], parity, ws);
-    phi_tile<S, 0>(a.sout, const_cast<double*>(a.phi), a.g, tr.tx, tr.ty);
+    phi_tile<S, 0>(a.sout, a.phi, const_cast<double*>(a.phi), a.g, tr.tx, tr.ty);
   }
 }
 

@@ -29,10 +29,11 @@ __global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(4))) void
 }
 
 template <class S, int BC>
-__global__ __launch_bounds__(S::NT) void k_phi(const float* __restrict__ snew, double* __restrict__ phi, Grid g) {
+__global__ __launch_bounds__(S::NT) void k_phi(const float* __restrict__ snew, const double* phi_in, double* phi_out,
+                                                Grid g) {
   int tx, ty;
   if (!xcd_tile((g.nx + S::TX - 1) / S::TX, (g.ny + S::TY - 1) / S::TY, tx, ty)) return;
-  phi_tile<S, BC>(snew, phi, g, tx, ty);
+  phi_tile<S, BC>(snew, phi_in, phi_out, g, tx, ty);
 }
 
 // Initial state, pass 1: node-local f^eq(P = 0, rho(phi0), u0) and
@@ -221,12 +222,13 @@ hipError_t dispatch(int form, int shape, const StepArgs& a, const MomentArgs& m,
 }
 
 template <class S>
-hipError_t launch_phi_t(const float* snew, double* phi, const Grid& g, int bc, hipStream_t s) {
+hipError_t launch_phi_t(const float* snew, const double* phi_in, double* phi_out, const Grid& g, int bc,
+                        hipStream_t s) {
   switch (bc) {
-    case 0: hipLaunchKernelGGL((k_phi<S, 0>), tile_grid<S>(g), dim3(S::NT), 0, s, snew, phi, g); break;
-    case 1: hipLaunchKernelGGL((k_phi<S, 1>), tile_grid<S>(g), dim3(S::NT), 0, s, snew, phi, g); break;
-    case 2: hipLaunchKernelGGL((k_phi<S, 2>), tile_grid<S>(g), dim3(S::NT), 0, s, snew, phi, g); break;
-    default: hipLaunchKernelGGL((k_phi<S, 3>), tile_grid<S>(g), dim3(S::NT), 0, s, snew, phi, g); break;
+    case 0: hipLaunchKernelGGL((k_phi<S, 0>), tile_grid<S>(g), dim3(S::NT), 0, s, snew, phi_in, phi_out, g); break;
+    case 1: hipLaunchKernelGGL((k_phi<S, 1>), tile_grid<S>(g), dim3(S::NT), 0, s, snew, phi_in, phi_out, g); break;
+    case 2: hipLaunchKernelGGL((k_phi<S, 2>), tile_grid<S>(g), dim3(S::NT), 0, s, snew, phi_in, phi_out, g); break;
+    default: hipLaunchKernelGGL((k_phi<S, 3>), tile_grid<S>(g), dim3(S::NT), 0, s, snew, phi_in, phi_out, g); break;
   }
   return hipGetLastError();
 }
@@ -241,12 +243,14 @@ hipError_t launch_moments(int form, const StepArgs& a, const MomentArgs& m, hipS
   return dispatch(form, 0, a, m, true, s);
 }
 
-hipError_t launch_phi(const float* snew, double* phi, const Grid& g, int wall_x, int wall_y, int shape, hipStream_t s) {
+hipError_t launch_phi(const float* snew, const double* phi_in, double* phi_out, const Grid& g, int wall_x, int wall_y,
+                      int shape, hipStream_t s) {
+  const int bc = wall_x | (wall_y << 1);
   switch (shape) {
-    case 1: return launch_phi_t<S1>(snew, phi, g, wall_x | (wall_y << 1), s);
-    case 2: return launch_phi_t<S2>(snew, phi, g, wall_x | (wall_y << 1), s);
-    case 3: return launch_phi_t<S3>(snew, phi, g, wall_x | (wall_y << 1), s);
-    default: return launch_phi_t<S0>(snew, phi, g, wall_x | (wall_y << 1), s);
+    case 1: return launch_phi_t<S1>(snew, phi_in, phi_out, g, bc, s);
+    case 2: return launch_phi_t<S2>(snew, phi_in, phi_out, g, bc, s);
+    case 3: return launch_phi_t<S3>(snew, phi_in, phi_out, g, bc, s);
+    default: return launch_phi_t<S0>(snew, phi_in, phi_out, g, bc, s);
   }
 }
 

@@ -815,7 +815,8 @@ __device__ __forceinline__ void fused_tile(Lds<S>& s, const StepArgs& a, const M
 // phi = sum h_i), from the state array just written (snew).  Both paths sum
 // in the same order.
 template <class S, int BC, bool FAST>
-__device__ __forceinline__ void phi_tile_impl(const float* __restrict__ snew, double* __restrict__ phi, const Grid& g,
+__device__ __forceinline__ void phi_tile_impl(const float* __restrict__ snew, const double* phi_in, double* phi_out,
+                                              const Grid& g,
                                               int tile_x, int tile_y) {
   constexpr int wx = (BC & 1) != 0, wy = (BC & 2) != 0;
   const int lx = threadIdx.x & (S::TX - 1), ty = threadIdx.x / S::TX;
@@ -846,13 +847,17 @@ __device__ __forceinline__ void phi_tile_impl(const float* __restrict__ snew, do
     PULL_PH(1) PULL_PH(2) PULL_PH(3) PULL_PH(4) PULL_PH(5) PULL_PH(6) PULL_PH(7) PULL_PH(8)
 #undef PULL_PH
   }
-  phi[(long long)y * g.pitch + x] += sum;
+  // phi_in may be phi_out (in place): a thread reads and writes only its node
+  phi_out[(long long)y * g.pitch + x] = phi_in[(long long)y * g.pitch + x] + sum;
 }
 
 template <class S, int BC>
-__device__ __forceinline__ void phi_tile(const float* snew, double* phi, const Grid& g, int tile_x, int tile_y) {
-  if (interior_tile<S>(tile_x * S::TX, tile_y * S::TY, g)) phi_tile_impl<S, BC, true>(snew, phi, g, tile_x, tile_y);
-  else phi_tile_impl<S, BC, false>(snew, phi, g, tile_x, tile_y);
+__device__ __forceinline__ void phi_tile(const float* snew, const double* phi_in, double* phi_out, const Grid& g,
+                                         int tile_x, int tile_y) {
+  if (interior_tile<S>(tile_x * S::TX, tile_y * S::TY, g))
+    phi_tile_impl<S, BC, true>(snew, phi_in, phi_out, g, tile_x, tile_y);
+  else
+    phi_tile_impl<S, BC, false>(snew, phi_in, phi_out, g, tile_x, tile_y);
 }
 
 // Tile shapes by index (kShapeTX/kShapeTY in lbm_internal.hpp).

@@ -108,19 +108,20 @@ class Sim:
 
 
 def run_forward(L):
-    for case in sorted(CASES):
+    cases = sorted(CASES)
+    for j, form in enumerate(FORMS):   # every form, the boundary set-ups in turn
+        case = cases[j % len(cases)]
         p, phi0, ux0, uy0 = CASES[case]()
-        for form in FORMS:
-            s = Sim(L, p, phi0, ux0, uy0)
-            s.step(6, form)
-            got = {k: v.astype(np.float64) for k, v in s.moments(form).items()}
-            op = oracle_params(p)
-            st = R.run(R.init(op, t64(phi0), t64(ux0), t64(uy0)), form, op, 6)
-            ref = {k: v.numpy() for k, v in R.moments(st, form, op).items()}
-            umax = float(np.sqrt(ref["ux"] ** 2 + ref["uy"] ** 2).max())
-            e = {"phi": float(np.abs(got["phi"] - ref["phi"]).max() / np.abs(ref["phi"]).max()),
-                 "u": float(max(np.abs(got["ux"] - ref["ux"]).max(), np.abs(got["uy"] - ref["uy"]).max()) / umax)}
-            print(json.dumps({"kind": "forward", "case": case, "form": form, **e}), flush=True)
+        s = Sim(L, p, phi0, ux0, uy0)
+        s.step(6, form)
+        got = {k: v.astype(np.float64) for k, v in s.moments(form).items()}
+        op = oracle_params(p)
+        st = R.run(R.init(op, t64(phi0), t64(ux0), t64(uy0)), form, op, 6)
+        ref = {k: v.numpy() for k, v in R.moments(st, form, op).items()}
+        umax = float(np.sqrt(ref["ux"] ** 2 + ref["uy"] ** 2).max())
+        e = {"phi": float(np.abs(got["phi"] - ref["phi"]).max() / np.abs(ref["phi"]).max()),
+             "u": float(max(np.abs(got["ux"] - ref["ux"]).max(), np.abs(got["uy"] - ref["uy"]).max()) / umax)}
+        print(json.dumps({"kind": "forward", "case": case, "form": form, **e}), flush=True)
 
 
 def run_adjoint(L):
@@ -129,8 +130,8 @@ def run_adjoint(L):
         for form in FORMS:
             k = 3
             op = oracle_params(p)
-            sig = torch.tensor(op.sigma, requires_grad=True)
-            M = torch.tensor(op.M, requires_grad=True)
+            sig = torch.tensor(op.sigma, dtype=torch.float64, requires_grad=True)
+            M = torch.tensor(op.M, dtype=torch.float64, requires_grad=True)
             st = R.run(R.init(op, t64(phi0), t64(ux0), t64(uy0)), form, op, k)
             f = st["f"].clone().requires_grad_(True)
             h = st["h"].clone().requires_grad_(True)

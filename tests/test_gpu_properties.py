@@ -200,3 +200,33 @@ def test_every_tile_shape_is_bitwise_equal(shape, case, monkeypatch):
     nd = int((a != b).sum())
     print(f"[tile shape] {case} shape {shape}: {nd} differing bytes of {a.size}", flush=True)
     assert nd == 0
+
+
+@pytest.mark.parametrize("case", ["shear_walls_stf2", "ragged_periodic_cpf1"])
+def test_step_blobs_equals_restore_step_save(case):
+    """lbm_step_blobs (one step from a saved state into another blob) gives
+    the blob that restore + lbm_step + lbm_save gives, bit for bit, and
+    leaves the simulation untouched."""
+    import paper_2012_14729_amd as P
+    if case == "shear_walls_stf2":
+        p, phi0, ux0, uy0 = WL.config_shear(nx=136, ny=44, R=12.0, Re=1.0, Ca=0.2)
+        form = "stf2"
+    else:
+        p = WL.ParamSet(nx=100, ny=72, rho1=10.0, rho2=1.0, nu1=0.1, nu2=0.2, sigma=5e-3, W=4.0, M=0.1, tau_h=0.8)
+        phi0, ux0, uy0, form = WL.two_droplets(100, 72, 12.0, 9.0, 2.0, 4.0), None, None, "cpf1"
+    sim = P.Simulation(p.as_dict(), np.asarray(phi0, np.float32), ux0, uy0)
+    sim.step(9, form)
+    b0 = sim.save()
+    here = sim.save()
+    b1 = torch.zeros_like(b0)
+    b2 = torch.zeros_like(b0)
+    sim.step_blobs(b0, b1, form)
+    sim.step_blobs(b1, b2, form)
+    assert torch.equal(sim.save(), here)   # the simulation is untouched
+    sim.restore(b0)
+    sim.step(1, form)
+    r1 = sim.save()
+    sim.step(1, form)
+    r2 = sim.save()
+    torch.cuda.synchronize()
+    assert torch.equal(b1, r1) and torch.equal(b2, r2)
