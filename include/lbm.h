@@ -241,6 +241,19 @@ int lbm_adjoint_step(lbm_adj* adj, int32_t force_form, const double* d_lambda_in
  * state; the simulation is not touched. */
 int lbm_adjoint_step_blob(lbm_adj* adj, const void* d_blob, int32_t force_form, const double* d_lambda_in,
                           double* d_lambda_out, void* stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * step as lbm_adjoint_step_blob, with its per-step scratch (15 FP64 values
+ * per node) in a 64 MiB array of the library's own, one per GPU, held until
+ * the process ends, instead of the adjoint workspace.  Lattices of at most
+ * 559240 nodes (nx*ny); larger ones return LBM_E_INVAL before any launch.
+ * Allocates nothing.  Every call on one GPU shares that GPU's array: calls
+ * that overlap in time on one GPU (different streams or host threads) race
+ * and give wrong results.  No state carries over between calls (every value
+ * the step reads from the array it has written in the same call).  The
+ * first call on a device looks the array's address up once. */
+int lbm_adjoint_step_blob_noalloc(lbm_adj* adj, const void* d_blob, int32_t force_form, const double* d_lambda_in,
+                                  double* d_lambda_out, void* stream);
 /* Adjoint of lbm_init (reading A11): dL/dphi0 (nx*ny FP64) from lambda_0,
  * and the initial state's contributions to dL/dsigma and dL/dM (replacing
  * those of an earlier call).  phi0, u0 as given to lbm_init. */

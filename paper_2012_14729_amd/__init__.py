@@ -277,6 +277,19 @@ class Adjoint:
                                           _stream(stream)))
         return out
 
+    def step_blob_noalloc(self, blob, lam, form, out, stream=None):
+        """step_blob through lbm_adjoint_step_blob_noalloc: its scratch is the
+        library's own per-GPU array, so the call allocates nothing (`out` is
+        required)."""
+        check_lambda(lam, self.sim.ny, self.sim.nx, self.workspace.device)
+        if not (torch.is_tensor(blob) and blob.dtype == torch.uint8 and blob.numel() == self.sim.state_bytes()
+                and blob.device == self.workspace.device):
+            raise ValueError("blob must be a uint8 tensor from Simulation.save() on the same device")
+        out = self._out(lam, out)
+        check(lib().lbm_adjoint_step_blob_noalloc(self._h, _ptr(blob), form_index(form), _ptr(lam), _ptr(out),
+                                                  _stream(stream)))
+        return out
+
     def init(self, lam, phi0, ux0=None, uy0=None, stream=None):
         dev = self.workspace.device
         check_lambda(lam, self.sim.ny, self.sim.nx, dev)

@@ -29,6 +29,7 @@
 // in a fixed order, so the results are deterministic.
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -838,6 +839,15 @@ hipError_t launch_adjoint(int form, const AArgs& A, hipStream_t st) {
 
 }  // namespace pflbm
 
+// Scratch of lbm_adjoint_step_blob_noalloc: the kNS FP64 planes that k_adj_a
+// writes and k_adj_b reads, for lattices of at most kNoallocNodes nodes.  One
+// copy lives on every GPU the library runs on, for the life of the process.
+// Host code reaches it only through the address hipGetSymbolAddress returns
+// on that device (noalloc_scratch below).
+constexpr size_t kNoallocBytes = size_t(64) << 20;   // 64 MiB
+constexpr long long kNoallocNodes = (long long)(kNoallocBytes / (pflbm::kNS * sizeof(double)));
+static __device__ __align__(256) double scratch[kNoallocBytes / sizeof(double)];
+
 using namespace pflbm;
 
 // ---------------------------------------------------------------------------
@@ -1020,6 +1030,51 @@ int lbm_adjoint_step_blob(lbm_adj* a, const void* d_blob, int32_t form, const do
   const char* b = (const char*)d_blob;   // lbm_save layout: state array, then phi
   const size_t sb = (size_t)kNPL * (size_t)a->sg.ps * sizeof(float);
   return adjoint_step_at(a, (const float*)b, (const double*)(b + sb), form, d_lambda_in, d_lambda_out, a->scr,
+                         (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Device address of `scratch` on the current device, looked up once per device.
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {};
+
+int noalloc_scratch(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return set_error(LBM_E_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return set_error(LBM_E_UNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return set_error(LBM_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = (double*)g_noalloc_ptr[dev];
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_adjoint_step_blob_noalloc(lbm_adj* a, const void* d_blob, int32_t form, const double* d_lambda_in,
+                                  double* d_lambda_out, void* stream) {
+  if (!a || !d_blob) return set_error(LBM_E_INVAL, "NULL argument");
+  const long long n = (long long)a->p.nx * a->p.ny;
+  if (n > kNoallocNodes)
+    return set_error(LBM_E_INVAL, "lattice of %lld nodes: lbm_adjoint_step_blob_noalloc takes at most %lld", n,
+                     kNoallocNodes);
+  double* scr = nullptr;
+  if (int r = noalloc_scratch(&scr)) return r;
+  const char* b = (const char*)d_blob;
+  const size_t sb = (size_t)kNPL * (size_t)a->sg.ps * sizeof(float);
+  return adjoint_step_at(a, (const float*)b, (const double*)(b + sb), form, d_lambda_in, d_lambda_out, scr,
                          (hipStream_t)stream);
 }
 

@@ -21,6 +21,8 @@ using std::isfinite;
 #define __forceinline__ inline
 #define __shared__ static
 #define __launch_bounds__(...)
+#define __align__(n) alignas(n)
+#define HIP_SYMBOL(x) (&(x))
 #define __restrict__ __restrict
 #define __builtin_amdgcn_rcpf(x) (1.0f / (x))
 #define __builtin_nontemporal_load(p) (*(p))
@@ -53,6 +55,8 @@ void hip_cpu_launch(const std::function<void()>& body, dim3 grid, dim3 block);
   hip_cpu_launch([&]() { kernel(__VA_ARGS__); }, dim3(grid), dim3(block))
 
 hipError_t hipGetLastError();
+hipError_t hipGetDevice(int* dev);
+hipError_t hipGetSymbolAddress(void** p, const void* symbol);
 const char* hipGetErrorString(hipError_t e);
 hipError_t hipMemcpyAsync(void* dst, const void* src, size_t bytes, hipMemcpyKind kind, hipStream_t s);
 hipError_t hipStreamSynchronize(hipStream_t s);
