@@ -38,6 +38,21 @@
 // ---------------------------------------------------------------------------
 namespace pflbm {
 
+// One tile of one instance, with everything the tile's first loads need (64
+// bytes, one scalar load): the instance's buffers as byte offsets into the
+// batch workspace (the kernels rebuild the pointers from the workspace base,
+// a kernel argument, so that they are known to address global memory) and
+// its grid.  The force form and constants come from the instance's Phys
+// entry, which is needed only after the order parameter has been staged.
+struct TileJob {
+  long long off_s[2];   // population buffers 0 and 1
+  long long off_phi;    // order parameter
+  int inst, form, tx, ty;
+  int nx, ny, pitch, rowe;
+  int fast, pad;
+};
+static_assert(sizeof(TileJob) == 64, "one 64-byte scalar load per tile");
+
 namespace {
 
 // Batched step: persistent workgroups walk a tile list covering every
@@ -62,16 +77,27 @@ __device__ __forceinline__ void batch_tile(Lds<S>& s, const StepArgs& a, int tx,
   else tile_impl<S, FORM, false, 0, false, true>(s, a, MomentArgs{}, tx, ty);
 }
 
-// Step arguments of a batch instance with its pointers rebuilt from the
-// workspace base, a kernel argument: pointers read from the descriptor would
-// be generic, and every access through them a flat one (which also counts
-// against the LDS wait counter).
-__device__ __forceinline__ StepArgs batch_args(const BatchInst& bi, int parity, char* ws) {
-  StepArgs a = bi.a[parity];
-  a.sin = (const float*)(ws + bi.off_s[parity]);
-  a.sout = (float*)(ws + bi.off_s[1 - parity]);
-  a.phi = (const double*)(ws + bi.off_phi);
-  a.status = (int*)(ws + bi.off_status);
+// Step arguments of a tile with its pointers rebuilt from the workspace base,
+// a kernel argument: pointers read from memory would be generic, and every
+// access through them a flat one (which also counts against the LDS wait
+// counter).
+__device__ __forceinline__ StepArgs batch_args(const TileJob& j, const Phys* phys, int* status, int parity, char* ws) {
+  StepArgs a;
+  // a conditional, not j.off_s[parity]: a run-time index into the local
+  // copy would place it in private memory
+  a.sin = (const float*)(ws + (parity ? j.off_s[1] : j.off_s[0]));
+  a.sout = (float*)(ws + (parity ? j.off_s[0] : j.off_s[1]));
+  a.phi = (const double*)(ws + j.off_phi);
+  a.status = status + j.inst;
+  a.g.nx = j.nx;
+  a.g.ny = j.ny;
+  a.g.pitch = j.pitch;
+  a.g.ncx = j.pitch >> 6;
+  a.g.ps = (long long)j.pitch * j.ny;
+  a.g.rowe = j.rowe;
+  a.g.fast = j.fast;
+  a.g.slip_x = a.g.slip_y = 0;   // periodic instances
+  a.c = phys[j.inst];
   return a;
 }
 
@@ -79,19 +105,19 @@ __device__ __forceinline__ StepArgs batch_args(const BatchInst& bi, int parity, 
 // sorted by form); FORM < 0: any form, dispatched per tile.
 template <class S, int FORM, bool FAST_OK>
 __global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_fused(
-    const BatchInst* __restrict__ inst, const TileRef* __restrict__ tiles, char* ws, int t0, int t1, int parity) {
+    const TileJob* __restrict__ jobs, const Phys* __restrict__ phys, int* status, char* ws, int t0, int t1,
+    int parity) {
   __shared__ Lds<S> s;
   int first, end, stride;
   band(t0, t1, first, end, stride);
   for (int t = first; t < end; t += stride) {
-    const TileRef tr = tiles[t];
-    const BatchInst& bi = inst[tr.inst];
+    const TileJob tr = jobs[t];
     __syncthreads();   // the previous tile is done with the LDS
-    const StepArgs a = batch_args(bi, parity, ws);
+    const StepArgs a = batch_args(tr, phys, status, parity, ws);
     if constexpr (FORM >= 0) {
       batch_tile<S, FORM, FAST_OK>(s, a, tr.tx, tr.ty);
     } else {
-      switch (bi.form) {
+      switch (tr.form) {
         case 0: batch_tile<S, 0, FAST_OK>(s, a, tr.tx, tr.ty); break;
         case 1: batch_tile<S, 1, FAST_OK>(s, a, tr.tx, tr.ty); break;
         case 2: batch_tile<S, 2, FAST_OK>(s, a, tr.tx, tr.ty); break;
@@ -105,16 +131,25 @@ __global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(4))) void
   }
 }
 
+// The order-parameter pass needs only the tile's own entry (no constants).
 template <class S>
-__global__ __launch_bounds__(S::NT) void k_batch_phi(const BatchInst* __restrict__ inst,
-                                                     const TileRef* __restrict__ tiles, char* ws, int ntiles,
+__global__ __launch_bounds__(S::NT) void k_batch_phi(const TileJob* __restrict__ jobs, char* ws, int ntiles,
                                                      int parity) {
   int first, end, stride;
   band(0, ntiles, first, end, stride);
   for (int t = first; t < end; t += stride) {
-    const TileRef tr = tiles[t];
-    const StepArgs a = batch_args(inst[tr.inst], parity, ws);
-    phi_tile<S, 0>(a.sout, a.phi, const_cast<double*>(a.phi), a.g, tr.tx, tr.ty);
+    const TileJob j = jobs[t];
+    Grid g;
+    g.nx = j.nx;
+    g.ny = j.ny;
+    g.pitch = j.pitch;
+    g.ncx = j.pitch >> 6;
+    g.ps = (long long)j.pitch * j.ny;
+    g.rowe = j.rowe;
+    g.fast = j.fast;
+    g.slip_x = g.slip_y = 0;
+    double* phi = (double*)(ws + j.off_phi);
+    phi_tile<S, 0>((const float*)(ws + (parity ? j.off_s[0] : j.off_s[1])), phi, phi, g, j.tx, j.ty);
   }
 }
 
@@ -125,49 +160,53 @@ __global__ __launch_bounds__(S::NT) void k_batch_phi(const BatchInst* __restrict
 namespace pflbm {
 
 template <class S, int FORM>
-void launch_batch_form(bool fast, dim3 grid, hipStream_t s, const BatchInst* inst, const TileRef* tiles, char* ws,
-                       int t0, int t1, int parity) {
+void launch_batch_form(bool fast, dim3 grid, hipStream_t s, const TileJob* jobs, const Phys* phys, int* status,
+                       char* ws, int t0, int t1, int parity) {
   if (fast)
-    hipLaunchKernelGGL((k_batch_fused<S, FORM, true>), grid, dim3(S::NT), 0, s, inst, tiles, ws, t0, t1, parity);
+    hipLaunchKernelGGL((k_batch_fused<S, FORM, true>), grid, dim3(S::NT), 0, s, jobs, phys, status, ws, t0, t1, parity);
   else
-    hipLaunchKernelGGL((k_batch_fused<S, FORM, false>), grid, dim3(S::NT), 0, s, inst, tiles, ws, t0, t1, parity);
+    hipLaunchKernelGGL((k_batch_fused<S, FORM, false>), grid, dim3(S::NT), 0, s, jobs, phys, status, ws, t0, t1,
+                       parity);
 }
 
 template <class S>
-void launch_batch_shape(int form, bool fast, dim3 grid, hipStream_t s, const BatchInst* inst, const TileRef* tiles,
-                        char* ws, int t0, int t1, int parity) {
+void launch_batch_shape(int form, bool fast, dim3 grid, hipStream_t s, const TileJob* jobs, const Phys* phys,
+                        int* status, char* ws, int t0, int t1, int parity) {
   switch (form) {
-    case 0: launch_batch_form<S, 0>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
-    case 1: launch_batch_form<S, 1>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
-    case 2: launch_batch_form<S, 2>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
-    case 3: launch_batch_form<S, 3>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
-    case 4: launch_batch_form<S, 4>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
-    case 5: launch_batch_form<S, 5>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
-    case 6: launch_batch_form<S, 6>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
-    case 7: launch_batch_form<S, 7>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
-    default: launch_batch_form<S, -1>(fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    case 0: launch_batch_form<S, 0>(fast, grid, s, jobs, phys, status, ws, t0, t1, parity); break;
+    case 1: launch_batch_form<S, 1>(fast, grid, s, jobs, phys, status, ws, t0, t1, parity); break;
+    case 2: launch_batch_form<S, 2>(fast, grid, s, jobs, phys, status, ws, t0, t1, parity); break;
+    case 3: launch_batch_form<S, 3>(fast, grid, s, jobs, phys, status, ws, t0, t1, parity); break;
+    case 4: launch_batch_form<S, 4>(fast, grid, s, jobs, phys, status, ws, t0, t1, parity); break;
+    case 5: launch_batch_form<S, 5>(fast, grid, s, jobs, phys, status, ws, t0, t1, parity); break;
+    case 6: launch_batch_form<S, 6>(fast, grid, s, jobs, phys, status, ws, t0, t1, parity); break;
+    case 7: launch_batch_form<S, 7>(fast, grid, s, jobs, phys, status, ws, t0, t1, parity); break;
+    default: launch_batch_form<S, -1>(fast, grid, s, jobs, phys, status, ws, t0, t1, parity); break;
   }
 }
 
-hipError_t launch_batch_fused(const BatchInst* inst, const TileRef* tiles, char* ws, int t0, int t1, int form,
+// Persistent batched step kernels over the tile range [t0, t1) of the tile
+// list (periodic instances); form < 0: one kernel for every form, else the
+// tiles all have that form.
+hipError_t launch_batch_fused(const TileJob* jobs, const Phys* phys, int* status, char* ws, int t0, int t1, int form,
                               int fast, int parity, int nblocks, int shape, hipStream_t s) {
   const dim3 grid(nblocks);
   switch (shape) {
-    case 1: launch_batch_shape<S1>(form, fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
-    case 2: launch_batch_shape<S2>(form, fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
-    case 3: launch_batch_shape<S3>(form, fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
-    default: launch_batch_shape<S0>(form, fast, grid, s, inst, tiles, ws, t0, t1, parity); break;
+    case 1: launch_batch_shape<S1>(form, fast, grid, s, jobs, phys, status, ws, t0, t1, parity); break;
+    case 2: launch_batch_shape<S2>(form, fast, grid, s, jobs, phys, status, ws, t0, t1, parity); break;
+    case 3: launch_batch_shape<S3>(form, fast, grid, s, jobs, phys, status, ws, t0, t1, parity); break;
+    default: launch_batch_shape<S0>(form, fast, grid, s, jobs, phys, status, ws, t0, t1, parity); break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_batch_phi(const BatchInst* inst, const TileRef* tiles, char* ws, int ntiles, int parity, int nblocks,
-                            int shape, hipStream_t s) {
+hipError_t launch_batch_phi(const TileJob* jobs, char* ws, int ntiles, int parity, int nblocks, int shape,
+                            hipStream_t s) {
   switch (shape) {
-    case 1: hipLaunchKernelGGL(k_batch_phi<S1>, dim3(nblocks), dim3(S1::NT), 0, s, inst, tiles, ws, ntiles, parity); break;
-    case 2: hipLaunchKernelGGL(k_batch_phi<S2>, dim3(nblocks), dim3(S2::NT), 0, s, inst, tiles, ws, ntiles, parity); break;
-    case 3: hipLaunchKernelGGL(k_batch_phi<S3>, dim3(nblocks), dim3(S3::NT), 0, s, inst, tiles, ws, ntiles, parity); break;
-    default: hipLaunchKernelGGL(k_batch_phi<S0>, dim3(nblocks), dim3(S0::NT), 0, s, inst, tiles, ws, ntiles, parity); break;
+    case 1: hipLaunchKernelGGL(k_batch_phi<S1>, dim3(nblocks), dim3(S1::NT), 0, s, jobs, ws, ntiles, parity); break;
+    case 2: hipLaunchKernelGGL(k_batch_phi<S2>, dim3(nblocks), dim3(S2::NT), 0, s, jobs, ws, ntiles, parity); break;
+    case 3: hipLaunchKernelGGL(k_batch_phi<S3>, dim3(nblocks), dim3(S3::NT), 0, s, jobs, ws, ntiles, parity); break;
+    default: hipLaunchKernelGGL(k_batch_phi<S0>, dim3(nblocks), dim3(S0::NT), 0, s, jobs, ws, ntiles, parity); break;
   }
   return hipGetLastError();
 }
@@ -244,8 +283,8 @@ BatchLayout layout(const lbm_params* p, int count) {
     L.ntiles = std::max(L.ntiles, n);
   }
   size_t o = 0;
-  L.desc = o; o = up(o + sizeof(BatchInst) * (size_t)count);
-  L.tiles = o; o = up(o + sizeof(TileRef) * (size_t)L.ntiles);
+  L.desc = o; o = up(o + sizeof(Phys) * (size_t)count);
+  L.tiles = o; o = up(o + sizeof(TileJob) * (size_t)L.ntiles);
   L.status = o; o = up(o + sizeof(int) * (size_t)count);
   L.sums = o; o = up(o + sizeof(double) * (size_t)count);
   L.partial = o; o = up(o + sizeof(double) * kPartials * (size_t)count);
@@ -283,6 +322,15 @@ int validate_one(const lbm_params* p, int k) {
 
 }  // namespace
 
+// Host copy of an instance's step arguments for both ping-pong parities
+// (a[p] reads population buffer p and writes buffer 1 - p), for the moments.
+struct BatchInst {
+  StepArgs a[2];
+  long long off_s[2];
+  long long off_phi, off_status;
+  int form;
+};
+
 struct lbm_batch {
   int count;
   BatchLayout L;
@@ -298,8 +346,8 @@ struct lbm_batch {
   BatchCfg cfg;                  // launch shape in use
   hipStream_t cap;               // private stream used only for graph capture
   hipGraphExec_t exec;           // kChunk steps starting from parity 0
-  BatchInst* d_inst() const { return (BatchInst*)(ws + L.desc); }
-  TileRef* d_tiles() const { return (TileRef*)(ws + L.tiles); }
+  Phys* d_phys() const { return (Phys*)(ws + L.desc); }
+  TileJob* d_tiles() const { return (TileJob*)(ws + L.tiles); }
   int* d_status() const { return (int*)(ws + L.status); }
 };
 
@@ -318,16 +366,16 @@ int launch_pair_steps(lbm_batch* b, const BatchCfg& c, int nsteps, int parity0, 
       for (int f = 0; f < LBM_NUM_FORMS; ++f) {
         const int t0 = b->form_beg[f], t1 = b->form_beg[f + 1];
         if (t1 > t0)
-          BHIP(launch_batch_fused(b->d_inst(), b->d_tiles(), b->ws, t0, t1, f, c.fast, par, grid_for(b, c, t1 - t0),
-                                  b->shape, st));
+          BHIP(launch_batch_fused(b->d_tiles(), b->d_phys(), b->d_status(), b->ws, t0, t1, f, c.fast, par,
+                                  grid_for(b, c, t1 - t0), b->shape, st));
       }
     } else {
-      BHIP(launch_batch_fused(b->d_inst(), b->d_tiles(), b->ws, 0, b->ntiles, -1, c.fast, par,
+      BHIP(launch_batch_fused(b->d_tiles(), b->d_phys(), b->d_status(), b->ws, 0, b->ntiles, -1, c.fast, par,
                               grid_for(b, c, b->ntiles), b->shape, st));
     }
     // The order-parameter pass holds few registers: one workgroup per tile
     // keeps far more of them resident than the fused kernel's persistent grid.
-    BHIP(launch_batch_phi(b->d_inst(), b->d_tiles(), b->ws, b->ntiles, par,
+    BHIP(launch_batch_phi(b->d_tiles(), b->ws, b->ntiles, par,
                           grid_for(b, BatchCfg{c.split, c.fast, 0, 0.0}, b->ntiles), b->shape, st));
     par = 1 - par;
   }
@@ -565,19 +613,36 @@ int lbm_batch_create(lbm_batch** out, const lbm_params* params, const int32_t* f
   std::vector<int> order(count);
   for (int k = 0; k < count; ++k) order[k] = k;
   std::stable_sort(order.begin(), order.end(), [&](int i, int j) { return forms[i] < forms[j]; });
-  std::vector<TileRef> tiles;
+  std::vector<TileJob> tiles;
   tiles.reserve(b->L.ntiles);
   for (int f = 0; f <= LBM_NUM_FORMS; ++f) b->form_beg[f] = 0;
   for (int k : order) {
     for (int f = forms[k] + 1; f <= LBM_NUM_FORMS; ++f) b->form_beg[f] += ntiles_of(params[k], b->shape);
     const int ntx = tiles_x(params[k], b->shape), nty = tiles_y(params[k], b->shape);
     for (int ty = 0; ty < nty; ++ty)
-      for (int tx = 0; tx < ntx; ++tx) tiles.push_back(TileRef{k, tx, ty, 0});
+      for (int tx = 0; tx < ntx; ++tx) {
+        const InstLayout& I = b->L.inst[k];
+        TileJob j{};
+        j.off_s[0] = (long long)I.s[0];
+        j.off_s[1] = (long long)I.s[1];
+        j.off_phi = (long long)I.phi;
+        j.inst = k;
+        j.form = forms[k];
+        j.tx = tx;
+        j.ty = ty;
+        j.nx = I.g.nx;
+        j.ny = I.g.ny;
+        j.pitch = I.g.pitch;
+        j.rowe = I.g.rowe;
+        j.fast = I.g.fast;
+        tiles.push_back(j);
+      }
   }
   b->ntiles = (int)tiles.size();
-  if (hipMemcpyAsync(ws + b->L.desc, b->host.data(), sizeof(BatchInst) * count, hipMemcpyHostToDevice, st) !=
-          hipSuccess ||
-      hipMemcpyAsync(ws + b->L.tiles, tiles.data(), sizeof(TileRef) * tiles.size(), hipMemcpyHostToDevice, st) !=
+  std::vector<Phys> phys(count);
+  for (int k = 0; k < count; ++k) phys[k] = b->host[k].a[0].c;
+  if (hipMemcpyAsync(ws + b->L.desc, phys.data(), sizeof(Phys) * count, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(ws + b->L.tiles, tiles.data(), sizeof(TileJob) * tiles.size(), hipMemcpyHostToDevice, st) !=
           hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return cleanup(bfail(LBM_E_HIP, "batch init: uploading descriptors"));

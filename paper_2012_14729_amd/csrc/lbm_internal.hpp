@@ -94,23 +94,6 @@ struct MomentArgs {
   float* ph;   // hydrodynamic pressure p_h = P_sf - D_form (Sec. II.B)
 };
 
-// One instance of a batch: its step arguments for both ping-pong parities
-// (a[p] reads population buffer p and writes buffer 1 - p) and its force form.
-// The kernels rebuild the pointers from byte offsets into the batch workspace
-// (a kernel argument), so that they are known to address global memory.
-struct BatchInst {
-  StepArgs a[2];
-  long long off_s[2];   // population buffers 0 and 1
-  long long off_phi, off_status;
-  int form;
-  int pad[3];
-};
-
-// One tile of one instance (tile indices in units of the batch's tile shape).
-struct TileRef {
-  int inst, tx, ty, pad;
-};
-
 // Records the thread-local message returned by lbm_last_error(); returns code.
 int set_error(int code, const char* fmt, ...);
 
@@ -149,12 +132,5 @@ hipError_t launch_fill_int(int* p, int value, int n, hipStream_t s);
 // zeros at `zero` (nullable), as one launch; sizes multiples of 4 bytes.
 hipError_t launch_copies(const void* const* src, void* const* dst, const size_t* bytes, int njobs, void* zero,
                          size_t zero_bytes, hipStream_t s);
-// persistent batched step kernels over a tile list (periodic instances); form < 0:
-// one kernel for every form, else the tiles [t0, t1) all have that form
-hipError_t launch_batch_fused(const BatchInst* inst, const TileRef* tiles, char* ws, int t0, int t1, int form,
-                              int fast, int parity, int nblocks, int shape, hipStream_t s);
-hipError_t launch_batch_phi(const BatchInst* inst, const TileRef* tiles, char* ws, int ntiles, int parity, int nblocks,
-                            int shape, hipStream_t s);
-int fused_blocks_per_cu(int shape);
 
 }  // namespace pflbm
