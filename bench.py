@@ -145,6 +145,12 @@ def bench_batched(steps, loop_steps):
     b = P.Batch(params, forms, phis)   # includes timing the candidate launch shapes
     create_s = time.perf_counter() - tc
     shape = b.config
+    classes = {}   # tile shapes chosen per instance-size class
+    for p_, ts in zip(params, b.tile_shapes()):
+        cls = "small (side <= 128)" if p_["nx"] <= 128 else ("medium (<= 320)" if p_["nx"] <= 320 else "large")
+        key = f"{ts[0]}x{ts[1]}"
+        classes.setdefault(cls, {}).setdefault(key, 0)
+        classes[cls][key] += 1
     b.step(16)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -175,9 +181,10 @@ def bench_batched(steps, loop_steps):
             "looping_plain_lbm_step_MLUPS": round(loop, 1), "loop_steps": loop_steps,
             "speedup_vs_loop": round(batched / loop, 2), "unstable_instances": len(unstable),
             "unstable": unstable,
-            "launch_shape": {"one_kernel_per_form": bool(shape["split"]), "interior_path": bool(shape["fast"]),
+            "launch_shape": {"one_kernel_per_form": bool(shape["split"]), "addressing": ("general", "interior", "wrapped")[shape["fast"]],
                              "workgroups_per_cu": shape["blocks_per_cu"] or "one per tile",
-                             "tuned_ms_per_step": round(shape["ms_per_step"], 4)},
+                             "tuned_ms_per_step": round(shape["ms_per_step"], 4),
+                             "tile_shapes_per_size_class": classes},
             "create_s_incl_tuning": round(create_s, 2)}
 
 
@@ -401,6 +408,9 @@ def main():
     if not args.no_batch:
         out["batched"] = bench_batched(args.batch_steps, 20)
         out["batched"]["vs_plain_step"] = round(out["batched"]["MLUPS"] / value, 3)
+        if out["spurious_current"]:   # the plain step's long-run rate (10^4 steps per form)
+            out["batched"]["vs_plain_step_long_run"] = round(
+                out["batched"]["MLUPS"] / out["spurious_current"]["MLUPS"], 3)
     if not args.no_adjoint:
         torch.cuda.empty_cache()
         out["adjoint"] = bench_adjoint(args.adjoint_steps)

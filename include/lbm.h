@@ -100,9 +100,10 @@ int lbm_workspace_bytes(const lbm_params* p, size_t* bytes);
  * The workspace must stay allocated until lbm_destroy.  The inputs may be
  * freed when the call returns (they are consumed on `stream`).
  * Tiles away from the domain edge use a faster addressing path with the
- * same arithmetic; the environment variable PFLBM_GENERAL_PATH=1, read here
- * and by lbm_batch_create, sends every tile through the general path
- * (diagnostics: both paths give bitwise identical states).  The step
+ * same arithmetic; the environment variable PFLBM_GENERAL_PATH, read here
+ * and by lbm_batch_create, sends every tile through the general path (=1),
+ * or turns off only the batched engine's wrapped path (=2) (diagnostics:
+ * every path gives bitwise identical states).  The step
  * kernels work on 64x8-node tiles; PFLBM_TILE=1, 2 or 3 (read here) runs a
  * periodic lattice's step on 32x16, 32x8 or 64x4 tiles instead (diagnostics
  * and tuning: every shape gives bitwise identical states). */
@@ -182,21 +183,32 @@ int lbm_destroy(lbm_sim* sim);
 int lbm_batch_workspace_bytes(const lbm_params* params, int32_t count, size_t* bytes);
 /* Initialise every instance (as lbm_init, u0 = 0) and choose the launch
  * shape of the batched step by timing the candidates on this batch (one
- * fused kernel for every form or one per form; interior addressing on or
- * off; persistent workgroups per CU or one per tile), unless a choice for
- * the same instance sizes and forms is cached in this process or in the
- * file named by PFLBM_TUNE_CACHE; PFLBM_BATCH_TUNE=0 skips the timing and
- * PFLBM_BATCH_CFG=split,fast,blocks_per_cu forces a shape.  The
+ * fused kernel for every form or one per form; addressing paths: general
+ * only, interior tiles on the interior path, or every tile on the wrapped
+ * path (when every instance's state array fits in 4 GiB); persistent
+ * workgroups per CU or one per tile), unless a choice for the same
+ * instance sizes and forms is cached in this process or in the file named
+ * by PFLBM_TUNE_CACHE; PFLBM_BATCH_TUNE=0 skips the timing and
+ * PFLBM_BATCH_CFG=split,paths,blocks_per_cu forces a shape.  The
  * timing steps run before the states are (re)initialised, so the returned
  * batch starts from phi0 either way.  Synchronises `stream`. */
 int lbm_batch_create(lbm_batch** batch, const lbm_params* params, const int32_t* forms, int32_t count,
                      void* d_ws, size_t ws_bytes, const float* const* d_phi0, void* stream);
 /* The launch shape in use: split = 1 if the fused step runs one launch per
- * force form, fast = 1 if interior tiles use the interior addressing path,
+ * force form, fast = the addressing paths (0 general, 1 interior tiles on
+ * the interior path and the others general, 2 every tile wrapped),
  * blocks_per_cu = persistent workgroups per CU (0: one per tile), and the
  * measured time per step in ms (0 when not timed).  Host-only. */
 int lbm_batch_config(const lbm_batch* batch, int32_t* split, int32_t* fast, int32_t* blocks_per_cu,
                      double* ms_per_step);
+/* Tile shape (tile_x x tile_y nodes) the batched step kernels use for
+ * instance k: the tuner picks one shape for every instance, or per instance
+ * 32x8 tiles where 64-wide ones would idle more lanes of the last tile
+ * column (else 64x8), whichever steps faster; PFLBM_BATCH_SHAPE (read by
+ * lbm_batch_create) forces one shape for every instance (0..3: 64x8,
+ * 32x16, 32x8, 64x4) or the per-instance choice (4).
+ * Host-only. */
+int lbm_batch_tile_shape(const lbm_batch* batch, int32_t k, int32_t* tile_x, int32_t* tile_y);
 /* Advance every instance by nsteps (asynchronous). */
 int lbm_batch_step(lbm_batch* batch, int32_t nsteps, void* stream);
 /* Moments of instance k, same definitions and layout as lbm_moments. */

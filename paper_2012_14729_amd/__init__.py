@@ -212,6 +212,15 @@ class Batch:
         check(lib().lbm_batch_config(self._h, C.byref(sp), C.byref(fa), C.byref(bp), C.byref(ms)))
         return {"split": sp.value, "fast": fa.value, "blocks_per_cu": bp.value, "ms_per_step": ms.value}
 
+    def tile_shapes(self):
+        """Tile shape (tile_x, tile_y) of every instance's step kernels."""
+        out = []
+        tx, ty = C.c_int32(), C.c_int32()
+        for k in range(self.count):
+            check(lib().lbm_batch_tile_shape(self._h, k, C.byref(tx), C.byref(ty)))
+            out.append((tx.value, ty.value))
+        return out
+
     def close(self):
         if getattr(self, "_h", None):
             lib().lbm_batch_destroy(self._h)

@@ -64,6 +64,7 @@ _SIGS = {
     "lbm_batch_status": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_void_p]),
     "lbm_batch_config": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                    C.POINTER(C.c_double)]),
+    "lbm_batch_tile_shape": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "lbm_batch_destroy": (C.c_int, [C.c_void_p]),
     "lbm_adjoint_workspace_bytes": (C.c_int, [C.POINTER(LbmParams), C.POINTER(C.c_size_t)]),
     "lbm_adjoint_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p, C.c_size_t]),

@@ -139,9 +139,11 @@ Layout layout_for(const lbm_params* p) {
   L.g.ncx = L.g.pitch / 64;
   L.g.ps = (long long)L.g.pitch * p->ny;
   L.g.rowe = L.g.ncx * kSegE;
-  L.g.fast = 1;
-  if (const char* e = std::getenv("PFLBM_GENERAL_PATH"))   // diagnostics: every tile on the general path
+  L.g.fast = fast_bits(L.g.ps);
+  if (const char* e = std::getenv("PFLBM_GENERAL_PATH")) {   // diagnostics: 1 every tile general, 2 no wrapped path
     if (e[0] == '1') L.g.fast = 0;
+    if (e[0] == '2') L.g.fast &= kFastInterior;
+  }
   L.g.slip_x = p->wall_x == 2;
   L.g.slip_y = p->wall_y == 2;
   const size_t sbytes = (size_t)kNPL * (size_t)L.g.ps * sizeof(float);

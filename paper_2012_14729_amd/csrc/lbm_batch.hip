@@ -6,9 +6,10 @@
 //   then, per instance, the same arrays as a single lattice (two interleaved
 //   state arrays, FP64 phi).
 // A step is launches over one tile list covering every instance (sorted by
-// force form): the fused collide-stream kernel (one launch for every form, or
-// one per form; persistent workgroups or one per tile) and the order-parameter
-// kernel (one workgroup per tile).  Steps are
+// tile shape, then force form): per tile shape, the fused collide-stream
+// kernel (one launch for every form, or one per form; persistent workgroups
+// or one per tile), then per tile shape the order-parameter kernel (one
+// workgroup per tile).  Steps are
 // replayed from a HIP graph captured once per batch (buffer A -> B -> A ...),
 // so the host issues one graph launch per kChunk steps.
 //
@@ -68,13 +69,19 @@ __device__ __forceinline__ void band(int t0, int t1, int& first, int& end, int& 
   stride = (int)(gridDim.x / kXcds);
 }
 
-// One tile of instance descriptor bi: FAST_OK lets interior tiles take the
-// interior addressing path (more registers); otherwise every tile takes the
-// general one.
-template <class S, int FORM, bool FAST_OK>
+// Addressing paths of a batched step kernel: every tile general (0);
+// interior tiles on the interior path, the others general (1); every tile
+// wrapped (2, when every instance's arrays allow it).  One kernel holds at
+// most two paths: the compiler merges the interior or general body with the
+// wrapped one into a single body that needs more registers than four waves
+// per SIMD allow (spills).
+constexpr int kBatchGeneral = 0, kBatchInterior = 1, kBatchWrapped = 2;
+
+template <class S, int FORM, int PATHS>
 __device__ __forceinline__ void batch_tile(Lds<S>& s, const StepArgs& a, int tx, int ty) {
-  if constexpr (FAST_OK) fused_tile<S, FORM, false, 0, true>(s, a, MomentArgs{}, tx, ty);
-  else tile_impl<S, FORM, false, 0, false, true>(s, a, MomentArgs{}, tx, ty);
+  if constexpr (PATHS == kBatchInterior) fused_tile<S, FORM, false, 0, true>(s, a, MomentArgs{}, tx, ty);
+  else if constexpr (PATHS == kBatchWrapped) tile_impl<S, FORM, false, 0, kPathWrapped, true>(s, a, MomentArgs{}, tx, ty);
+  else tile_impl<S, FORM, false, 0, kPathGeneral, true>(s, a, MomentArgs{}, tx, ty);
 }
 
 // Step arguments of a tile with its pointers rebuilt from the workspace base,
@@ -103,7 +110,7 @@ __device__ __forceinline__ StepArgs batch_args(const TileJob& j, const Phys* phy
 
 // FORM >= 0: every tile of [t0, t1) has that force form (the tile list is
 // sorted by form); FORM < 0: any form, dispatched per tile.
-template <class S, int FORM, bool FAST_OK>
+template <class S, int FORM, int PATHS>
 __global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_fused(
     const TileJob* __restrict__ jobs, const Phys* __restrict__ phys, int* status, char* ws, int t0, int t1,
     int parity) {
@@ -115,17 +122,17 @@ __global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(4))) void
     __syncthreads();   // the previous tile is done with the LDS
     const StepArgs a = batch_args(tr, phys, status, parity, ws);
     if constexpr (FORM >= 0) {
-      batch_tile<S, FORM, FAST_OK>(s, a, tr.tx, tr.ty);
+      batch_tile<S, FORM, PATHS>(s, a, tr.tx, tr.ty);
     } else {
       switch (tr.form) {
-        case 0: batch_tile<S, 0, FAST_OK>(s, a, tr.tx, tr.ty); break;
-        case 1: batch_tile<S, 1, FAST_OK>(s, a, tr.tx, tr.ty); break;
-        case 2: batch_tile<S, 2, FAST_OK>(s, a, tr.tx, tr.ty); break;
-        case 3: batch_tile<S, 3, FAST_OK>(s, a, tr.tx, tr.ty); break;
-        case 4: batch_tile<S, 4, FAST_OK>(s, a, tr.tx, tr.ty); break;
-        case 5: batch_tile<S, 5, FAST_OK>(s, a, tr.tx, tr.ty); break;
-        case 6: batch_tile<S, 6, FAST_OK>(s, a, tr.tx, tr.ty); break;
-        default: batch_tile<S, 7, FAST_OK>(s, a, tr.tx, tr.ty); break;
+        case 0: batch_tile<S, 0, PATHS>(s, a, tr.tx, tr.ty); break;
+        case 1: batch_tile<S, 1, PATHS>(s, a, tr.tx, tr.ty); break;
+        case 2: batch_tile<S, 2, PATHS>(s, a, tr.tx, tr.ty); break;
+        case 3: batch_tile<S, 3, PATHS>(s, a, tr.tx, tr.ty); break;
+        case 4: batch_tile<S, 4, PATHS>(s, a, tr.tx, tr.ty); break;
+        case 5: batch_tile<S, 5, PATHS>(s, a, tr.tx, tr.ty); break;
+        case 6: batch_tile<S, 6, PATHS>(s, a, tr.tx, tr.ty); break;
+        default: batch_tile<S, 7, PATHS>(s, a, tr.tx, tr.ty); break;
       }
     }
   }
@@ -133,10 +140,10 @@ __global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(4))) void
 
 // The order-parameter pass needs only the tile's own entry (no constants).
 template <class S>
-__global__ __launch_bounds__(S::NT) void k_batch_phi(const TileJob* __restrict__ jobs, char* ws, int ntiles,
+__global__ __launch_bounds__(S::NT) void k_batch_phi(const TileJob* __restrict__ jobs, char* ws, int t0, int t1,
                                                      int parity) {
   int first, end, stride;
-  band(0, ntiles, first, end, stride);
+  band(t0, t1, first, end, stride);
   for (int t = first; t < end; t += stride) {
     const TileJob j = jobs[t];
     Grid g;
@@ -149,7 +156,7 @@ __global__ __launch_bounds__(S::NT) void k_batch_phi(const TileJob* __restrict__
     g.fast = j.fast;
     g.slip_x = g.slip_y = 0;
     double* phi = (double*)(ws + j.off_phi);
-    phi_tile<S, 0>((const float*)(ws + (parity ? j.off_s[0] : j.off_s[1])), phi, phi, g, j.tx, j.ty);
+    phi_tile<S, 0, true>((const float*)(ws + (parity ? j.off_s[0] : j.off_s[1])), phi, phi, g, j.tx, j.ty);
   }
 }
 
@@ -160,17 +167,21 @@ __global__ __launch_bounds__(S::NT) void k_batch_phi(const TileJob* __restrict__
 namespace pflbm {
 
 template <class S, int FORM>
-void launch_batch_form(bool fast, dim3 grid, hipStream_t s, const TileJob* jobs, const Phys* phys, int* status,
+void launch_batch_form(int paths, dim3 grid, hipStream_t s, const TileJob* jobs, const Phys* phys, int* status,
                        char* ws, int t0, int t1, int parity) {
-  if (fast)
-    hipLaunchKernelGGL((k_batch_fused<S, FORM, true>), grid, dim3(S::NT), 0, s, jobs, phys, status, ws, t0, t1, parity);
+  if (paths == kBatchInterior)
+    hipLaunchKernelGGL((k_batch_fused<S, FORM, kBatchInterior>), grid, dim3(S::NT), 0, s, jobs, phys, status, ws, t0,
+                       t1, parity);
+  else if (paths == kBatchWrapped)
+    hipLaunchKernelGGL((k_batch_fused<S, FORM, kBatchWrapped>), grid, dim3(S::NT), 0, s, jobs, phys, status, ws, t0,
+                       t1, parity);
   else
-    hipLaunchKernelGGL((k_batch_fused<S, FORM, false>), grid, dim3(S::NT), 0, s, jobs, phys, status, ws, t0, t1,
-                       parity);
+    hipLaunchKernelGGL((k_batch_fused<S, FORM, kBatchGeneral>), grid, dim3(S::NT), 0, s, jobs, phys, status, ws, t0,
+                       t1, parity);
 }
 
 template <class S>
-void launch_batch_shape(int form, bool fast, dim3 grid, hipStream_t s, const TileJob* jobs, const Phys* phys,
+void launch_batch_shape(int form, int fast, dim3 grid, hipStream_t s, const TileJob* jobs, const Phys* phys,
                         int* status, char* ws, int t0, int t1, int parity) {
   switch (form) {
     case 0: launch_batch_form<S, 0>(fast, grid, s, jobs, phys, status, ws, t0, t1, parity); break;
@@ -200,13 +211,13 @@ hipError_t launch_batch_fused(const TileJob* jobs, const Phys* phys, int* status
   return hipGetLastError();
 }
 
-hipError_t launch_batch_phi(const TileJob* jobs, char* ws, int ntiles, int parity, int nblocks, int shape,
+hipError_t launch_batch_phi(const TileJob* jobs, char* ws, int t0, int t1, int parity, int nblocks, int shape,
                             hipStream_t s) {
   switch (shape) {
-    case 1: hipLaunchKernelGGL(k_batch_phi<S1>, dim3(nblocks), dim3(S1::NT), 0, s, jobs, ws, ntiles, parity); break;
-    case 2: hipLaunchKernelGGL(k_batch_phi<S2>, dim3(nblocks), dim3(S2::NT), 0, s, jobs, ws, ntiles, parity); break;
-    case 3: hipLaunchKernelGGL(k_batch_phi<S3>, dim3(nblocks), dim3(S3::NT), 0, s, jobs, ws, ntiles, parity); break;
-    default: hipLaunchKernelGGL(k_batch_phi<S0>, dim3(nblocks), dim3(S0::NT), 0, s, jobs, ws, ntiles, parity); break;
+    case 1: hipLaunchKernelGGL(k_batch_phi<S1>, dim3(nblocks), dim3(S1::NT), 0, s, jobs, ws, t0, t1, parity); break;
+    case 2: hipLaunchKernelGGL(k_batch_phi<S2>, dim3(nblocks), dim3(S2::NT), 0, s, jobs, ws, t0, t1, parity); break;
+    case 3: hipLaunchKernelGGL(k_batch_phi<S3>, dim3(nblocks), dim3(S3::NT), 0, s, jobs, ws, t0, t1, parity); break;
+    default: hipLaunchKernelGGL(k_batch_phi<S0>, dim3(nblocks), dim3(S0::NT), 0, s, jobs, ws, t0, t1, parity); break;
   }
   return hipGetLastError();
 }
@@ -217,10 +228,10 @@ int fused_blocks_per_cu(int shape) {
   int n = 0;
   hipError_t e;
   switch (shape) {
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_fused<S1, -1, true>, S1::NT, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_fused<S2, -1, true>, S2::NT, 0); break;
-    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_fused<S3, -1, true>, S3::NT, 0); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_fused<S0, -1, true>, S0::NT, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_fused<S1, -1, kBatchInterior>, S1::NT, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_fused<S2, -1, kBatchInterior>, S2::NT, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_fused<S3, -1, kBatchInterior>, S3::NT, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_fused<S0, -1, kBatchInterior>, S0::NT, 0); break;
   }
   return (e != hipSuccess || n < 1) ? 1 : n;
 }
@@ -261,26 +272,40 @@ struct BatchLayout {
   int ntiles;
 };
 
+// Tile-shape policies: 0..kNumShapes-1 give every instance that shape;
+// kPolicyFit gives an instance 32x8 tiles where 64-wide ones would leave
+// more lanes of its last tile column idle, else 64x8 (sides that are not a
+// multiple of 64; measured on 32..512-node instances: 6-7 % faster steps
+// for the instances up to 320 nodes wide).
+constexpr int kPolicyFit = kNumShapes;
+
 // Launch shape of the batched step.
 struct BatchCfg {
-  int split;   // 1: one fused launch per force form; 0: one launch for every form
-  int fast;    // interior tiles may take the interior addressing path
-  int bpc;     // persistent workgroups per CU; 0: one workgroup per tile
-  double ms;   // measured time per step (ms), 0 if not timed
+  int split;    // 1: one fused launch per force form and tile shape; 0: one launch per tile shape
+  int fast;     // addressing paths: kBatchGeneral, kBatchInterior or kBatchWrapped
+  int bpc;      // persistent workgroups per CU; 0: one workgroup per tile
+  int policy;   // tile-shape policy
+  double ms;    // measured time per step (ms), 0 if not timed
 };
 
-int tiles_x(const lbm_params& p, int shape) { return (p.nx + kShapeTX[shape] - 1) / kShapeTX[shape]; }
-int tiles_y(const lbm_params& p, int shape) { return (p.ny + kShapeTY[shape] - 1) / kShapeTY[shape]; }
-int ntiles_of(const lbm_params& p, int shape) { return tiles_x(p, shape) * tiles_y(p, shape); }
+int tiles_x(int nx, int shape) { return (nx + kShapeTX[shape] - 1) / kShapeTX[shape]; }
+int tiles_y(int ny, int shape) { return (ny + kShapeTY[shape] - 1) / kShapeTY[shape]; }
+int ntiles_of(int nx, int ny, int shape) { return tiles_x(nx, shape) * tiles_y(ny, shape); }
 
-// Room for the tile list of any shape: the most tiles any shape gives.
+int shape_for(int nx, int policy) {
+  if (policy < kNumShapes) return policy;
+  const int idle64 = tiles_x(nx, 0) * kShapeTX[0] - nx, idle32 = tiles_x(nx, 2) * kShapeTX[2] - nx;
+  return idle32 < idle64 ? 2 : 0;
+}
+
+// Room for the tile list of any policy: each instance's most tiles.
 BatchLayout layout(const lbm_params* p, int count) {
   BatchLayout L{};
   L.ntiles = 0;
-  for (int sh = 0; sh < kNumShapes; ++sh) {
+  for (int k = 0; k < count; ++k) {
     int n = 0;
-    for (int k = 0; k < count; ++k) n += ntiles_of(p[k], sh);
-    L.ntiles = std::max(L.ntiles, n);
+    for (int sh = 0; sh < kNumShapes; ++sh) n = std::max(n, ntiles_of(p[k].nx, p[k].ny, sh));
+    L.ntiles += n;
   }
   size_t o = 0;
   L.desc = o; o = up(o + sizeof(Phys) * (size_t)count);
@@ -297,9 +322,11 @@ BatchLayout layout(const lbm_params* p, int count) {
     I.g.ncx = I.g.pitch / 64;
     I.g.ps = (long long)I.g.pitch * p[k].ny;
     I.g.rowe = I.g.ncx * kSegE;
-    I.g.fast = 1;
-    if (const char* e = std::getenv("PFLBM_GENERAL_PATH"))
+    I.g.fast = fast_bits(I.g.ps);
+    if (const char* e = std::getenv("PFLBM_GENERAL_PATH")) {
       if (e[0] == '1') I.g.fast = 0;
+      if (e[0] == '2') I.g.fast &= kFastInterior;
+    }
     const size_t sbytes = (size_t)kNPL * (size_t)I.g.ps * sizeof(float);
     for (int b = 0; b < 2; ++b) { I.s[b] = o; o = up(o + sbytes); }
     I.phi = o; o = up(o + (size_t)I.g.ps * sizeof(double));
@@ -340,9 +367,15 @@ struct lbm_batch {
   int parity;                    // population buffer holding the current state
   int64_t step;
   int cus;                       // compute units of the device
-  int shape;                     // tile shape of the step kernels (index into kShapeTX/kShapeTY)
+  int forced_policy;             // PFLBM_BATCH_SHAPE, or -1
+  bool wrap_ok;                  // every instance allows the wrapped addressing path
+  int policy;                    // tile-shape policy of the uploaded tile list
+  std::vector<int> ishape;       // tile shape of each instance under that policy
   int ntiles;                    // tiles of the list in use
-  int form_beg[LBM_NUM_FORMS + 1];   // tile range of each force form in the sorted list
+  // tile list sorted by shape, then force form, then instance: the tiles of
+  // shape sh and form f are [grp[sh][f], grp[sh][f + 1]), those of shape sh
+  // [grp[sh][0], grp[sh][LBM_NUM_FORMS])
+  int grp[kNumShapes][LBM_NUM_FORMS + 1];
   BatchCfg cfg;                  // launch shape in use
   hipStream_t cap;               // private stream used only for graph capture
   hipGraphExec_t exec;           // kChunk steps starting from parity 0
@@ -359,27 +392,95 @@ int grid_for(const lbm_batch* b, const BatchCfg& c, int n) {
   return std::max(8, (std::min(want, n) + 7) / 8 * 8);
 }
 
+// The step launches of the uploaded tile list (its policy is c.policy).
 int launch_pair_steps(lbm_batch* b, const BatchCfg& c, int nsteps, int parity0, hipStream_t st) {
   int par = parity0;
+  const BatchCfg one_per_tile{c.split, c.fast, 0, c.policy, 0.0};
   for (int n = 0; n < nsteps; ++n) {
-    if (c.split) {
-      for (int f = 0; f < LBM_NUM_FORMS; ++f) {
-        const int t0 = b->form_beg[f], t1 = b->form_beg[f + 1];
-        if (t1 > t0)
-          BHIP(launch_batch_fused(b->d_tiles(), b->d_phys(), b->d_status(), b->ws, t0, t1, f, c.fast, par,
-                                  grid_for(b, c, t1 - t0), b->shape, st));
+    for (int sh = 0; sh < kNumShapes; ++sh) {
+      const int* g = b->grp[sh];
+      if (g[LBM_NUM_FORMS] == g[0]) continue;
+      if (c.split) {
+        for (int f = 0; f < LBM_NUM_FORMS; ++f)
+          if (g[f + 1] > g[f])
+            BHIP(launch_batch_fused(b->d_tiles(), b->d_phys(), b->d_status(), b->ws, g[f], g[f + 1], f, c.fast, par,
+                                    grid_for(b, c, g[f + 1] - g[f]), sh, st));
+      } else {
+        BHIP(launch_batch_fused(b->d_tiles(), b->d_phys(), b->d_status(), b->ws, g[0], g[LBM_NUM_FORMS], -1, c.fast,
+                                par, grid_for(b, c, g[LBM_NUM_FORMS] - g[0]), sh, st));
       }
-    } else {
-      BHIP(launch_batch_fused(b->d_tiles(), b->d_phys(), b->d_status(), b->ws, 0, b->ntiles, -1, c.fast, par,
-                              grid_for(b, c, b->ntiles), b->shape, st));
     }
     // The order-parameter pass holds few registers: one workgroup per tile
     // keeps far more of them resident than the fused kernel's persistent grid.
-    BHIP(launch_batch_phi(b->d_tiles(), b->ws, b->ntiles, par,
-                          grid_for(b, BatchCfg{c.split, c.fast, 0, 0.0}, b->ntiles), b->shape, st));
+    for (int sh = 0; sh < kNumShapes; ++sh) {
+      const int* g = b->grp[sh];
+      if (g[LBM_NUM_FORMS] > g[0])
+        BHIP(launch_batch_phi(b->d_tiles(), b->ws, g[0], g[LBM_NUM_FORMS], par,
+                              grid_for(b, one_per_tile, g[LBM_NUM_FORMS] - g[0]), sh, st));
+    }
     par = 1 - par;
   }
   return LBM_OK;
+}
+
+// Sort the tiles of every instance by the shape `policy` gives it, then by
+// force form, and upload the list (synchronises st).
+int build_tiles(lbm_batch* b, int policy, hipStream_t st) {
+  const int count = b->count;
+  b->ishape.resize(count);
+  for (int k = 0; k < count; ++k) b->ishape[k] = shape_for(b->L.inst[k].g.nx, policy);
+  std::vector<int> order(count);
+  for (int k = 0; k < count; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(), [&](int i, int j) {
+    return b->ishape[i] != b->ishape[j] ? b->ishape[i] < b->ishape[j] : b->forms[i] < b->forms[j];
+  });
+  std::vector<TileJob> tiles;
+  tiles.reserve(b->L.ntiles);
+  int k_at = 0;
+  for (int sh = 0; sh < kNumShapes; ++sh)
+    for (int f = 0; f <= LBM_NUM_FORMS; ++f) {
+      // first tile of (sh, f): append the instances of this group
+      b->grp[sh][f] = (int)tiles.size();
+      if (f == LBM_NUM_FORMS) break;
+      for (; k_at < count && b->ishape[order[k_at]] == sh && b->forms[order[k_at]] == f; ++k_at) {
+        const int k = order[k_at];
+        const InstLayout& I = b->L.inst[k];
+        const int ntx = tiles_x(I.g.nx, sh), nty = tiles_y(I.g.ny, sh);
+        for (int ty = 0; ty < nty; ++ty)
+          for (int tx = 0; tx < ntx; ++tx) {
+            TileJob j{};
+            j.off_s[0] = (long long)I.s[0];
+            j.off_s[1] = (long long)I.s[1];
+            j.off_phi = (long long)I.phi;
+            j.inst = k;
+            j.form = f;
+            j.tx = tx;
+            j.ty = ty;
+            j.nx = I.g.nx;
+            j.ny = I.g.ny;
+            j.pitch = I.g.pitch;
+            j.rowe = I.g.rowe;
+            j.fast = I.g.fast;
+            tiles.push_back(j);
+          }
+      }
+    }
+  if (k_at != count || (int)tiles.size() > b->L.ntiles) return bfail(LBM_E_INVAL, "batch tile list: internal error");
+  b->ntiles = (int)tiles.size();
+  b->policy = policy;
+  if (hipMemcpyAsync(b->ws + b->L.tiles, tiles.data(), sizeof(TileJob) * tiles.size(), hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return bfail(LBM_E_HIP, "batch: uploading the tile list");
+  return LBM_OK;
+}
+
+// Resident workgroups per CU of the fused kernel for the shapes in use.
+int occupancy(const lbm_batch* b) {
+  int occ = 64;
+  for (int sh = 0; sh < kNumShapes; ++sh)
+    if (b->grp[sh][LBM_NUM_FORMS] > b->grp[sh][0]) occ = std::min(occ, fused_blocks_per_cu(sh));
+  return occ;
 }
 
 int build_graph(lbm_batch* b) {
@@ -397,11 +498,12 @@ int build_graph(lbm_batch* b) {
 }
 
 // Key of a batch for the tuning cache: device size, instance sizes, forms.
-uint64_t signature(const lbm_params* p, const int32_t* forms, int count, int cus, int shape) {
+uint64_t signature(const lbm_params* p, const int32_t* forms, int count, int cus, int forced_policy, bool wrap_ok) {
   uint64_t h = 1469598103934665603ull;
   auto mix = [&](uint64_t v) { h = (h ^ v) * 1099511628211ull; };
   mix((uint64_t)cus);
-  mix((uint64_t)shape);
+  mix((uint64_t)(forced_policy + 1));
+  mix((uint64_t)wrap_ok);
   mix((uint64_t)count);
   for (int k = 0; k < count; ++k) {
     mix((uint64_t)p[k].nx);
@@ -426,7 +528,8 @@ void read_tune_file() {   // g_tune_mu held
   if (!f) return;
   unsigned long long key;
   BatchCfg c{};
-  while (fscanf(f, "%llx %d %d %d %lf", &key, &c.split, &c.fast, &c.bpc, &c.ms) == 5) g_tune[(uint64_t)key] = c;
+  while (fscanf(f, "%llx %d %d %d %d %lf", &key, &c.split, &c.fast, &c.bpc, &c.policy, &c.ms) == 6)
+    g_tune[(uint64_t)key] = c;
   fclose(f);
 }
 
@@ -434,7 +537,7 @@ void append_tune_file(uint64_t key, const BatchCfg& c) {   // g_tune_mu held
   const char* path = tune_file();
   if (!path) return;
   if (FILE* f = fopen(path, "a")) {
-    fprintf(f, "%016llx %d %d %d %.6f\n", (unsigned long long)key, c.split, c.fast, c.bpc, c.ms);
+    fprintf(f, "%016llx %d %d %d %d %.6f\n", (unsigned long long)key, c.split, c.fast, c.bpc, c.policy, c.ms);
     fclose(f);
   }
 }
@@ -479,45 +582,62 @@ int init_states(lbm_batch* b, const lbm_params* params, const float* const* d_ph
 // on this batch (the timing steps change the state; it is rebuilt after).
 int choose_cfg(lbm_batch* b, const lbm_params* params, const int32_t* forms, const float* const* d_phi0,
                hipStream_t st) {
-  const int occ = fused_blocks_per_cu(b->shape);
-  const BatchCfg dflt{1, 1, occ, 0.0};
-  if (const char* fc = std::getenv("PFLBM_BATCH_CFG")) {   // forced shape "split,fast,blocks_per_cu"
-    BatchCfg c{0, 0, 0, 0.0};
+  const int policy0 = b->forced_policy >= 0 ? b->forced_policy : 0;
+  const BatchCfg dflt{1, b->wrap_ok ? kBatchWrapped : kBatchInterior, 0, policy0, 0.0};
+  if (const char* fc = std::getenv("PFLBM_BATCH_CFG")) {   // forced shape "split,paths,blocks_per_cu"
+    BatchCfg c{0, 0, 0, policy0, 0.0};
     if (sscanf(fc, "%d,%d,%d", &c.split, &c.fast, &c.bpc) != 3 || c.split < 0 || c.split > 1 || c.fast < 0 ||
-        c.fast > 1 || c.bpc < 0 || c.bpc > 64)
-      return bfail(LBM_E_INVAL, "PFLBM_BATCH_CFG must be split,fast,blocks_per_cu (0/1, 0/1, 0..64)");
+        c.fast > 2 || c.bpc < 0 || c.bpc > 64)
+      return bfail(LBM_E_INVAL, "PFLBM_BATCH_CFG must be split,paths,blocks_per_cu (0/1, 0..2, 0..64)");
+    if (c.fast == kBatchWrapped && !b->wrap_ok)
+      return bfail(LBM_E_INVAL, "PFLBM_BATCH_CFG: the wrapped path needs every instance's arrays within 4 GiB");
     b->cfg = c;
-    return LBM_OK;
+    return build_tiles(b, c.policy, st);
   }
   const char* tv = std::getenv("PFLBM_BATCH_TUNE");
   if (tv && tv[0] == '0') {
     b->cfg = dflt;
-    return LBM_OK;
+    return build_tiles(b, dflt.policy, st);
   }
-  const uint64_t key = signature(params, forms, b->count, b->cus, b->shape);
+  const uint64_t key = signature(params, forms, b->count, b->cus, b->forced_policy, b->wrap_ok);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     read_tune_file();
     auto it = g_tune.find(key);
-    if (it != g_tune.end()) {
+    const bool usable = it != g_tune.end() && (it->second.fast != kBatchWrapped || b->wrap_ok) &&
+                        it->second.policy >= 0 && it->second.policy <= kPolicyFit &&
+                        (b->forced_policy < 0 || it->second.policy == b->forced_policy);
+    if (usable) {
       b->cfg = it->second;
-      return LBM_OK;
+      return build_tiles(b, b->cfg.policy, st);
     }
   }
   BatchCfg best = dflt;
   best.ms = 1e300;
-  for (int split = 0; split <= 1; ++split)
-    for (int fast = 0; fast <= 1; ++fast)
-      for (int bpc : {1, 2, 0}) {
-        if (bpc > occ) continue;
-        BatchCfg c{split, fast, bpc, 0.0};
-        double ms = 0.0;
-        if (int r = time_cfg(b, c, st, &ms)) return r;
-        if (ms < best.ms) {
-          best = c;
-          best.ms = ms;
+  std::vector<int> policies;
+  if (b->forced_policy >= 0) policies = {b->forced_policy};
+  else policies = {0, 2, kPolicyFit};
+  std::vector<std::vector<int>> seen;
+  for (int pol : policies) {
+    if (int r = build_tiles(b, pol, st)) return r;
+    if (std::find(seen.begin(), seen.end(), b->ishape) != seen.end()) continue;   // same tiles as a policy timed
+    seen.push_back(b->ishape);
+    const int occ = occupancy(b);
+    for (int split = 0; split <= 1; ++split)
+      for (int fast = 0; fast <= (b->wrap_ok ? 2 : 1); ++fast)
+        for (int bpc : {1, 2, 0}) {
+          if (bpc > occ) continue;
+          BatchCfg c{split, fast, bpc, pol, 0.0};
+          double ms = 0.0;
+          if (int r = time_cfg(b, c, st, &ms)) return r;
+          if (ms < best.ms) {
+            best = c;
+            best.ms = ms;
+          }
         }
-      }
+  }
+  if (b->policy != best.policy)
+    if (int r = build_tiles(b, best.policy, st)) return r;
   if (int r = init_states(b, params, d_phi0, st, false)) return r;
   b->cfg = best;
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -561,14 +681,18 @@ int lbm_batch_create(lbm_batch** out, const lbm_params* params, const int32_t* f
   b->step = 0;
   b->cap = nullptr;
   b->exec = nullptr;
-  b->shape = 0;
-  if (const char* e = std::getenv("PFLBM_BATCH_SHAPE")) {   // diagnostics: force a tile shape
+  b->forced_policy = -1;
+  b->policy = -1;
+  b->ntiles = 0;
+  b->wrap_ok = true;
+  for (int k = 0; k < count; ++k) b->wrap_ok = b->wrap_ok && (b->L.inst[k].g.fast & kFastWrap);
+  if (const char* e = std::getenv("PFLBM_BATCH_SHAPE")) {   // diagnostics: force a tile-shape policy
     const int sh = atoi(e);
-    if (sh < 0 || sh >= kNumShapes) {
+    if (sh < 0 || sh > kPolicyFit) {
       delete b;
-      return bfail(LBM_E_INVAL, "PFLBM_BATCH_SHAPE must be 0..%d", kNumShapes - 1);
+      return bfail(LBM_E_INVAL, "PFLBM_BATCH_SHAPE must be 0..%d", kPolicyFit);
     }
-    b->shape = sh;
+    b->forced_policy = sh;
   }
   hipStream_t st = (hipStream_t)stream;
   auto cleanup = [&](int code) {
@@ -609,41 +733,9 @@ int lbm_batch_create(lbm_batch** out, const lbm_params* params, const int32_t* f
     b->host[k].off_status = (long long)((char*)(b->d_status() + k) - ws);
     b->host[k].form = forms[k];
   }
-  // tile list: by force form, then instance, then row-major tiles
-  std::vector<int> order(count);
-  for (int k = 0; k < count; ++k) order[k] = k;
-  std::stable_sort(order.begin(), order.end(), [&](int i, int j) { return forms[i] < forms[j]; });
-  std::vector<TileJob> tiles;
-  tiles.reserve(b->L.ntiles);
-  for (int f = 0; f <= LBM_NUM_FORMS; ++f) b->form_beg[f] = 0;
-  for (int k : order) {
-    for (int f = forms[k] + 1; f <= LBM_NUM_FORMS; ++f) b->form_beg[f] += ntiles_of(params[k], b->shape);
-    const int ntx = tiles_x(params[k], b->shape), nty = tiles_y(params[k], b->shape);
-    for (int ty = 0; ty < nty; ++ty)
-      for (int tx = 0; tx < ntx; ++tx) {
-        const InstLayout& I = b->L.inst[k];
-        TileJob j{};
-        j.off_s[0] = (long long)I.s[0];
-        j.off_s[1] = (long long)I.s[1];
-        j.off_phi = (long long)I.phi;
-        j.inst = k;
-        j.form = forms[k];
-        j.tx = tx;
-        j.ty = ty;
-        j.nx = I.g.nx;
-        j.ny = I.g.ny;
-        j.pitch = I.g.pitch;
-        j.rowe = I.g.rowe;
-        j.fast = I.g.fast;
-        tiles.push_back(j);
-      }
-  }
-  b->ntiles = (int)tiles.size();
   std::vector<Phys> phys(count);
   for (int k = 0; k < count; ++k) phys[k] = b->host[k].a[0].c;
   if (hipMemcpyAsync(ws + b->L.desc, phys.data(), sizeof(Phys) * count, hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(ws + b->L.tiles, tiles.data(), sizeof(TileJob) * tiles.size(), hipMemcpyHostToDevice, st) !=
-          hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return cleanup(bfail(LBM_E_HIP, "batch init: uploading descriptors"));
   int dev = 0, cus = 0;
@@ -702,6 +794,13 @@ int lbm_batch_config(const lbm_batch* b, int32_t* split, int32_t* fast, int32_t*
   *fast = b->cfg.fast;
   *blocks_per_cu = b->cfg.bpc;
   *ms_per_step = b->cfg.ms;
+  return LBM_OK;
+}
+
+int lbm_batch_tile_shape(const lbm_batch* b, int32_t k, int32_t* tile_x, int32_t* tile_y) {
+  if (!b || k < 0 || k >= b->count || !tile_x || !tile_y) return bfail(LBM_E_INVAL, "bad batch, instance or pointer");
+  *tile_x = kShapeTX[b->ishape[k]];
+  *tile_y = kShapeTY[b->ishape[k]];
   return LBM_OK;
 }
 

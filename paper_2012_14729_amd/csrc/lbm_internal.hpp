@@ -66,9 +66,18 @@ struct Grid {
   int ncx;                // 64-node row segments per row (pitch / 64)
   long long ps;           // nodes of a padded plane (pitch * ny)
   int rowe;               // elements of one row of a state array (ncx * 21 * 64)
-  int fast;               // interior tiles may take the fast addressing path
+  int fast;               // addressing paths allowed (kFastInterior | kFastWrap)
   int slip_x, slip_y;     // the walls of that axis are free-slip (specular), not no-slip
 };
+
+// Grid::fast bits.  kFastInterior: interior tiles address from a tile
+// origin.  kFastWrap: the other tiles of a periodic lattice address with
+// 32-bit byte offsets from the state array's base, which needs the array
+// within 4 GiB (fast_bits below).
+constexpr int kFastInterior = 1, kFastWrap = 2;
+__host__ __device__ constexpr int fast_bits(long long plane_nodes) {
+  return kFastInterior | ((long long)kNPL * plane_nodes * 4 <= 0xffffffffLL ? kFastWrap : 0);
+}
 
 // Element index of plane 0 of node (x, y) in a state array (21 ps < 2^32 is
 // validated); plane p of the node is 64 p elements further.

@@ -81,11 +81,11 @@ def wide_batch():
 
 
 @pytest.mark.parametrize("cfg", ["0,0,1", "0,1,1", "0,0,2", "0,1,2", "0,1,0", "1,0,1", "1,1,1", "1,0,2",
-                                 "1,1,2", "1,0,0", "1,1,0", "0,0,0"])
+                                 "1,1,2", "1,0,0", "1,1,0", "0,0,0", "0,2,0", "0,2,1", "1,2,0", "1,2,2"])
 def test_every_launch_shape_matches_single_lattice(cfg, monkeypatch):
-    """Whatever launch shape the tuner picks (one kernel or one per form,
-    interior addressing on or off, persistent or one workgroup per tile), the
-    instances evolve bit for bit as single lattices."""
+    """Whatever launch shape the tuner picks (one kernel or one per form;
+    general, interior or wrapped addressing; persistent or one workgroup
+    per tile), the instances evolve bit for bit as single lattices."""
     import paper_2012_14729_amd as P
     params, forms, phis = wide_batch()
     monkeypatch.setenv("PFLBM_BATCH_CFG", cfg)
@@ -115,7 +115,7 @@ def test_tuned_batch_starts_from_phi0(monkeypatch):
     tuned = P.Batch([p.as_dict() for p in params], forms, phis)
     cfg = tuned.config
     print(f"[batch] tuned shape {cfg}", flush=True)
-    assert cfg["ms_per_step"] > 0 and cfg["split"] in (0, 1) and cfg["fast"] in (0, 1) and cfg["blocks_per_cu"] >= 0
+    assert cfg["ms_per_step"] > 0 and cfg["split"] in (0, 1) and cfg["fast"] in (0, 1, 2) and cfg["blocks_per_cu"] >= 0
     monkeypatch.setenv("PFLBM_BATCH_TUNE", "0")
     plain = P.Batch([p.as_dict() for p in params], forms, phis)
     for b in (tuned, plain):
@@ -127,17 +127,26 @@ def test_tuned_batch_starts_from_phi0(monkeypatch):
             assert torch.equal(mt[key], mp[key]), (k, key)
 
 
-@pytest.mark.parametrize("shape", [0, 1, 2, 3])
-@pytest.mark.parametrize("cfg", ["1,1,2", "0,1,0"])
+@pytest.mark.parametrize("shape", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("cfg", ["1,1,2", "0,1,0", "1,2,0"])
 def test_every_tile_shape_matches_single_lattice(shape, cfg, monkeypatch):
-    """Batched step kernels in every tile shape (PFLBM_BATCH_SHAPE) evolve
-    the instances bit for bit as single lattices."""
+    """Batched step kernels in every tile shape (PFLBM_BATCH_SHAPE 0-3), and
+    with a shape per instance (4: 32x8 where 64-wide tiles idle more lanes,
+    so 64x8 and 32x8 tiles share the batch), evolve the instances bit for
+    bit as single lattices."""
     import paper_2012_14729_amd as P
     params, forms, phis = wide_batch()
     monkeypatch.setenv("PFLBM_BATCH_CFG", cfg)
     monkeypatch.setenv("PFLBM_BATCH_SHAPE", str(shape))
     b = P.Batch([p.as_dict() for p in params], forms, phis)
     monkeypatch.delenv("PFLBM_BATCH_SHAPE", raising=False)
+    shapes = [(64, 8), (32, 16), (32, 8), (64, 4)]
+    if shape < 4:
+        want = [shapes[shape]] * len(params)
+    else:   # the 32-wide shape where it leaves fewer idle lanes in the last tile column
+        want = [(32, 8) if (-p.nx) % 32 < (-p.nx) % 64 else (64, 8) for p in params]
+        assert len(set(want)) == 2
+    assert b.tile_shapes() == want
     b.step(19)
     torch.cuda.synchronize()
     assert not any(b.status())
