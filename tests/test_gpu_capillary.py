@@ -1,8 +1,12 @@
 """End-to-end physics of the GPU path: a capillary wave (Sec. V.C) released
-from rest, density ratio 1, H = 80 (box 80 x 240, periodic x, no-slip top
-and bottom, Re = 50, We = 1, h0 = 0.01 H).  Its amplitude follows the
-analytic solution (Eqs. 44-46) with the time-averaged error E2 (Eq. 47)
-that the paper prints in Table III for each force form."""
+from rest, H = 80 (box 80 x 240, periodic x, no-slip top and bottom, We = 1,
+h0 = 0.01 H) at density ratios 1 (Re = 50) and 10 (Re = 50/sqrt(10), the
+paper's physical set-up with the lower fluid ten times heavier), W = 4 and
+Pe = 1/Cn as the opening of Sec. V prescribes (M = 5.3, tau_h = 1.5).  Its
+amplitude follows the analytic solution (Eqs. 44-46) with the time-averaged
+error E2 (Eq. 47) that Table III prints for each force form.  CPF-1 and PF-2
+diverge at this Peclet number (the paper reports them as the forms that need
+a larger one) and are not run here."""
 import json
 import os
 
@@ -11,22 +15,26 @@ import torch
 
 pytestmark = pytest.mark.gpu
 
+STABLE = ["stf1", "stf2", "cpf2", "pf1", "csf1", "csf2"]
 
-@pytest.mark.parametrize("form", ["stf2", "cpf2", "pf1", "csf2"])
-def test_capillary_wave_error_matches_table3(form):
+
+@pytest.mark.parametrize("ratio", [1, 10])
+@pytest.mark.parametrize("form", STABLE)
+def test_capillary_wave_error_matches_table3(form, ratio):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2012_14729_amd.benchmarks import capillary_wave
     tab = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table3_capillary.json")))
-    printed = tab["E2"]["ratio1_H80"][tab["forms"].index(form)]
-    print(f"[capillary] {form} H=80", flush=True)
-    r = capillary_wave(form, H=80)
-    print(f"[capillary]   E2={r['E2']:.4f} (Table III {printed})", flush=True)
+    printed = tab["E2"][f"ratio{ratio}_H80"][tab["forms"].index(form)]
+    print(f"[capillary] {form} H=80 density ratio {ratio}", flush=True)
+    r = capillary_wave(form, H=80, rho_ratio=1.0 / ratio)
+    print(f"[capillary]   E2={r['E2']:.4f} (Table III {printed}) M={r['M']:.3f} tau_h={r['tau_h']}", flush=True)
     assert not r["diverged"]
-    assert abs(r["E2"] - printed) < 0.25 * printed + 0.005
+    assert abs(r["E2"] - printed) < 0.3 * printed + 0.003
     # the first quarter period: the wave crosses zero within 8 % of the analytic
-    # time (the diffuse interface, W = 4 on a wavelength of 80, slows it by ~5 %)
+    # time (the diffuse interface, W = 4 on a wavelength of 80, slows it)
     t, h, th = r["t"], r["h"], r["theory"]
+
     def first(a):
         i = int(((a[1:] < 0) & (a[:-1] >= 0)).nonzero()[0][0])
         return t[i] + (t[i + 1] - t[i]) * a[i] / (a[i] - a[i + 1])

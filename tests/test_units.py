@@ -75,3 +75,39 @@ def test_taylor_deformation_matches_printed_theory_row():
     tab = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table6_taylor.json")))
     for ca, d in zip(tab["Ca"], tab["theory_rho1"]):
         assert abs(U.taylor_deformation(ca, 1.0) - d) < 6e-5, (ca, d)
+
+
+def test_capillary_wave_parameters_follow_the_paper_recipe():
+    """Sec. V.C with Pe = 1/Cn (opening of Sec. V): H = 80, W = 4, U_c = 0.0125
+    gives nu = 0.02, sigma = 0.0125 and M = U_c H / (4 beta Pe) = 5.33; the
+    density-ratio-10 case keeps nu, sigma and H of the physical set-up with
+    the lower fluid ten times heavier, so Re = 50 / sqrt(10)."""
+    from paper_2012_14729_amd.benchmarks import capillary_params
+    p = capillary_params(80)
+    assert math.isclose(p["nu1"], 0.02) and math.isclose(p["nu2"], 0.02)
+    assert math.isclose(p["sigma"], 0.0125) and math.isclose(p["M"], 16.0 / 3.0)
+    assert p["wall_y"] == 1 and p["nx"] == 80 and p["ny"] == 240 and p["tau_h"] == 1.5
+    g = U.groups_of(p, 80.0, 0.0125)
+    assert math.isclose(g.Re, 50.0) and math.isclose(g.We, 1.0) and math.isclose(g.Pe, 1.0 / g.Cn)
+    # physical set-up of the ratio-10 run: H = 1, nu = 0.01, sigma = 0.25, rho = 10 below, 1 above
+    Uc = math.sqrt(0.25 / (1.0 * 10.0))
+    p10 = capillary_params(80, rho_ratio=0.1)
+    assert math.isclose(U.groups_of(p10, 80.0, 0.0125).Re, Uc * 1.0 / 0.01)
+    assert math.isclose(p10["rho2"] / p10["rho1"], 0.1) and math.isclose(p10["nu1"], p10["nu2"])
+    assert math.isclose(capillary_params(160)["M"], 8.0 / 3.0)
+
+
+def test_rising_bubble_parameters_follow_the_paper_recipe():
+    """Sec. V.D (Table IV: Re = 35, Eo = 10, density and viscosity ratios 10)
+    with W = 4 and Pe = 1/Cn on the 240 x 480 mesh: L_c = 2R = 120,
+    U_g = 0.05, g = U_g^2 / L_c, sigma = U_g^2 L_c / Eo, M = 8.89."""
+    from paper_2012_14729_amd.benchmarks import bubble_params
+    p = bubble_params(240)
+    L, Ug = 120.0, 0.05
+    assert math.isclose(-p["gy"], Ug * Ug / L) and p["gx"] == 0.0
+    assert math.isclose(p["sigma"], Ug * Ug * L / 10.0)
+    assert math.isclose(Ug * L / p["nu1"], 35.0)
+    assert math.isclose(p["rho2"], 0.1) and math.isclose(p["rho2"] * p["nu2"], 0.1 * p["nu1"])
+    beta = 3 * p["sigma"] / (4 * 4.0)
+    assert math.isclose(Ug * L / (4 * p["M"] * beta), L / 4.0)   # Pe = 1/Cn
+    assert p["wall_x"] == 2 and p["wall_y"] == 1 and (p["nx"], p["ny"]) == (240, 480)
