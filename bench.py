@@ -222,8 +222,10 @@ def bench_adjoint(T):
     plain = cells * T / (time.perf_counter() - t0) / 1e6
     del s
     P.adjoint_gradients(pd, "stf2", 16, phi0, target, ux, uy)   # warm-up
-    tm = {}
+    tm, tms = {}, {}
+    P.adjoint_gradients(pd, "stf2", T, phi0, target, ux, uy, timings=tms, overlap=False)
     loss, dphi0, dsig, dM = P.adjoint_gradients(pd, "stf2", T, phi0, target, ux, uy, timings=tm)
+    bwd_serial = cells * T / tms["backward_s"] / 1e6
     fwd = cells * T / tm["forward_s"] / 1e6
     bwd = cells * T / tm["backward_s"] / 1e6
     tot = cells * T / (tm["forward_s"] + tm["backward_s"]) / 1e6
@@ -235,7 +237,10 @@ def bench_adjoint(T):
             "forward_with_checkpoints_MLUPS": round(fwd, 1),
             "backward_MLUPS": round(bwd, 1), "gradient_MLUPS": round(tot, 1),
             "backward_vs_plain_step": round(bwd / plain, 3), "gradient_vs_plain_step": round(tot / plain, 3),
-            "backward_note": "adjoint steps (FP64) plus the recompute of each segment from its checkpoint",
+            "backward_serial_MLUPS": round(bwd_serial, 1),
+            "backward_note": "adjoint steps (FP64) plus the recompute of each segment from its checkpoint, "
+                             "the next segment's recompute on a second stream during the current adjoint "
+                             "(serial: one stream)",
             "loss": loss, "dL_dsigma": dsig, "dL_dM": dM, "max_abs_dL_dphi0": float(dphi0.abs().max())}
 
 

@@ -357,47 +357,101 @@ class _Checkpointed:
     def forward(self, keep_checkpoints=True):
         sim = self.sim
         if keep_checkpoints:
-            for t in range(self.T):
-                if t % self.every == 0:
-                    self.ckpt.append(sim.save())
-                sim.step(1, self.form)
+            for t in range(0, self.T, self.every):
+                self.ckpt.append(sim.save())
+                sim.step(min(self.every, self.T - t), self.form)
         else:
             sim.step(self.T, self.form)
         self.lam, self.loss = self.adj.seed_phi_misfit(self.target)
         return self.loss
 
-    def backward(self):
+    def backward(self, overlap=True):
+        """The adjoint pass.  overlap: recompute the next segment's states on
+        a second stream (two pools, alternating) while the adjoint steps of
+        the current one run; the kernels and their inputs are the same, so
+        the results are bitwise those of the serial order."""
         if self.lam is None or (self.T > 0 and not self.ckpt):
             raise RuntimeError("backward needs a forward pass that kept its checkpoints")
         sim, adj, lam, every = self.sim, self.adj, self.lam, self.every
         spare = torch.empty_like(lam)   # lambda ping-pongs between two arrays
         npool = min(every, self.T) - 1
-        pool = [torch.zeros_like(self.ckpt[0]) for _ in range(npool)] if self.ckpt else []
-        for s in reversed(range(len(self.ckpt))):
+        nseg = len(self.ckpt)
+        overlap = overlap and nseg > 1 and npool > 0
+        pools = [[torch.zeros_like(self.ckpt[0]) for _ in range(npool)] if self.ckpt else []
+                 for _ in range(2 if overlap else 1)]
+        main = torch.cuda.current_stream(lam.device)
+        side = torch.cuda.Stream(device=lam.device) if overlap else main   # default priority
+        # The loops below issue two library calls per step; arguments are
+        # validated here once (blobs from save() of this simulation, lambda
+        # arrays by the checks of Adjoint.step_blob), so the calls go straight
+        # to the C ABI and the host keeps ahead of the GPU.
+        check_lambda(lam, sim.ny, sim.nx, adj.workspace.device)
+        check_lambda(spare, sim.ny, sim.nx, adj.workspace.device)
+        nbytes = sim.state_bytes()
+        for b in [c for c in self.ckpt if c is not None] + [b for pl in pools for b in pl]:
+            if not (b.dtype == torch.uint8 and b.numel() == nbytes and b.device == adj.workspace.device):
+                raise ValueError("checkpoint blobs must come from Simulation.save() of this simulation")
+        L, fi, sh, ah = lib(), form_index(self.form), sim._h, adj._h
+        s_main, s_side = _stream(main), _stream(side)
+        ready = [None] * nseg    # segment s recomputed (recorded on `side`)
+        freed = [None, None]     # pool k no longer read by the adjoint (recorded on `main`)
+        if overlap:
+            side.wait_stream(main)   # the forward pass and the zeroed pools are complete
+
+        def recompute(s, k):
             t_lo, t_hi = s * every, min(self.T, (s + 1) * every)
-            states = [self.ckpt[s]] + pool[:t_hi - t_lo - 1]
+            states = [self.ckpt[s]] + pools[k][:t_hi - t_lo - 1]
+            if overlap:
+                if freed[k] is not None:
+                    side.wait_event(freed[k])
+                self.ckpt[s].record_stream(side)
             for j in range(1, t_hi - t_lo):
-                sim.step_blobs(states[j - 1], states[j], self.form)
+                check(L.lbm_step_blobs(sh, _ptr(states[j - 1]), _ptr(states[j]), fi, s_side))
+            if overlap:
+                ready[s] = torch.cuda.Event()
+                ready[s].record(side)
+            return states
+
+        segs = list(reversed(range(nseg)))
+        states_next = recompute(segs[0], 0) if (segs and overlap) else None
+        for i, s in enumerate(segs):
+            k = i % len(pools)
+            if overlap:
+                states = states_next
+                if i + 1 < len(segs):   # the next segment's recompute goes ahead of this segment's adjoint
+                    states_next = recompute(segs[i + 1], (i + 1) % len(pools))
+            else:
+                states = recompute(s, 0)
+            if overlap:
+                main.wait_event(ready[s])
+            t_lo, t_hi = s * every, min(self.T, (s + 1) * every)
             for t in reversed(range(t_lo, t_hi)):
-                adj.step_blob(states[t - t_lo], lam, self.form, out=spare)
+                check(L.lbm_adjoint_step_blob(ah, _ptr(states[t - t_lo]), fi, _ptr(lam), _ptr(spare), s_main))
                 lam, spare = spare, lam
+            if overlap:
+                freed[k] = torch.cuda.Event()
+                freed[k].record(main)
             self.ckpt[s] = None   # this checkpoint is no longer needed
-        del pool
+        if overlap:
+            main.wait_stream(side)
+        del pools
         self.ckpt = []
         dphi0 = adj.init(lam, self.phi0, self.ux0, self.uy0)
         dsig, dM = adj.param_grads()
         return dphi0, dsig, dM
 
 
-def adjoint_gradients(params, form, T, phi0, target, ux0=None, uy0=None, every=None, timings=None):
+def adjoint_gradients(params, form, T, phi0, target, ux0=None, uy0=None, every=None, timings=None, overlap=True):
     """dL/dphi0, dL/dsigma, dL/dM of L = 1/2 sum (phi_T - target)^2.
 
     Forward T steps keeping a state checkpoint every `every` steps (default
     ceil(sqrt(T))), then the adjoint backwards: each segment is recomputed
     from its checkpoint (one state per step, held for that segment only) and
     the adjoint steps run over it in reverse.  Memory: (T/every + every)
-    states.  `timings`, if a dict, receives the forward and backward wall
-    times (seconds, synchronised).  Returns (loss, dphi0 [float64], dsigma, dM)."""
+    states (twice `every` with `overlap`, which recomputes the next segment on
+    a second stream during the adjoint of the current one).  `timings`, if a
+    dict, receives the forward and backward wall times (seconds,
+    synchronised).  Returns (loss, dphi0 [float64], dsigma, dM)."""
     sync = timings is not None
     if sync:
         torch.cuda.synchronize()
@@ -408,7 +462,7 @@ def adjoint_gradients(params, form, T, phi0, target, ux0=None, uy0=None, every=N
     if sync:
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-    dphi0, dsig, dM = run.backward()
+    dphi0, dsig, dM = run.backward(overlap=overlap)
     if sync:
         torch.cuda.synchronize()
         timings["forward_s"] = t1 - t0

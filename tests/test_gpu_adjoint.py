@@ -269,3 +269,30 @@ def test_rollout_forward_is_one_forward_and_backward_runs_the_adjoint():
     L.backward()
     assert float(sg.grad) == ds_ref and float(mm.grad) == dm_ref
     assert torch.equal(ph.grad, dphi_ref.to(torch.float32))
+
+
+@pytest.mark.parametrize("T,every", [(150, None), (37, 8), (9, 4)])
+def test_overlapped_backward_equals_serial(T, every):
+    """The backward pass that recomputes the next segment on a second stream
+    while the adjoint runs over the current one gives the serial order's
+    gradients bit for bit (same kernels, same inputs; two state pools)."""
+    import paper_2012_14729_amd as P
+    p, phi0, ux0, uy0 = WL.config_shear(nx=96, ny=48, R=12.0, Re=1.0, Ca=0.2)
+    form = "cpf2"
+    dev = torch.device("cuda")
+    f32 = lambda a: torch.tensor(np.asarray(a, np.float32), device=dev)   # noqa: E731
+    phi0_t, ux, uy = f32(phi0), f32(ux0), f32(uy0)
+    s = P.Simulation(dict(p.as_dict(), sigma=1.2 * p.sigma), phi0_t, ux, uy, device=dev)
+    s.step(T, form)
+    target = s.moments(form)["phi"]
+    del s
+    out = []
+    for overlap in (False, True):
+        run = P._Checkpointed(p.as_dict(), form, T, phi0_t, target, ux, uy, every)
+        loss = run.forward()
+        out.append((loss, *run.backward(overlap=overlap)))
+    torch.cuda.synchronize()
+    (l0, d0, s0, m0), (l1, d1, s1, m1) = out
+    print(f"[overlap] T={T} every={every}: L {l0:.6e}, dL/dsigma {s0:.6e} / {s1:.6e}", flush=True)
+    assert l0 == l1 and s0 == s1 and m0 == m1
+    assert torch.equal(d0, d1)
