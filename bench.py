@@ -44,11 +44,16 @@ BYTES_PHI = 4 + 8 * 4 + 8 + 8
 FORMS = ("stf1", "stf2", "cpf1", "cpf2", "pf1", "pf2", "csf1", "csf2")
 TIMING_PERIOD = 8   # kernel durations: HIP events on one step in eight of the timed region
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fused_droplet2048.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2012_14729_amd", "csrc", "lbm_kernels.hip")
+# sources of the fused step kernel: the launchers, the tile body and the shared declarations
+KERNEL_SRC = [os.path.join(ROOT, "paper_2012_14729_amd", "csrc", f)
+              for f in ("lbm_kernels.hip", "lbm_tile.hpp", "lbm_internal.hpp")]
 
 
 def kernel_sha():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():
