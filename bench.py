@@ -120,6 +120,7 @@ def cpu_baseline(budget_all_s=15.0, budget_one_s=12.0):
     finally:
         torch.set_num_threads(prev)
     model, logical = _host_cpu()
+    small = oracle_droplet64(threads)
     all_rate = cells * n_all / el_all / 1e6
     one_rate = cells * n_one / el_one / 1e6
     return {"value": round(all_rate, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
@@ -127,7 +128,48 @@ def cpu_baseline(budget_all_s=15.0, budget_one_s=12.0):
                       f"{threads} threads) after 1 warm-up step, {el_all:.1f} s",
             "one_core": {"value": round(one_rate, 3), "unit": "MLUPS", "cores": 1,
                          "sample": f"{n_one} further time steps on 1 thread, {el_one:.1f} s"},
-            "host": {"cpu_model": model, "logical_cpus_on_host": logical, "cpus_available_to_process": avail}}
+            "host": {"cpu_model": model, "logical_cpus_on_host": logical, "cpus_available_to_process": avail},
+            "oracle_droplet64": small}
+
+
+def oracle_droplet64(threads, steps=1000):
+    """The 64x64 stationary droplet (R = 16, W = 4, density ratio 10, sigma =
+    0.01, tau_f = tau_h = 0.8, CPF-2) run by the oracle alone for 1000 steps,
+    timed on `threads` cores, with its Laplace-law check (sigma from R_num
+    (p_in - p_out), Sec. V.A) and the drift of sum(phi).  The pressure still
+    rings acoustically at 1000 steps (period about 75 steps, +-40 %), so sigma
+    is the mean of ten samples 25 steps apart over the last 250 steps."""
+    import numpy as np
+    import torch
+
+    import workloads as WL
+    from oracle import lbm_ref as R
+
+    p, phi0, _, _ = WL.config_droplet64()
+    op = R.Params(**{k: (None if k == "rho0" else v) for k, v in p.as_dict().items()})
+    prev = torch.get_num_threads()
+    try:
+        torch.set_num_threads(threads)
+        st = R.init(op, torch.tensor(np.asarray(phi0, np.float32), dtype=torch.float64))
+        s0 = float(R.moments(st, "cpf2", op)["phi"].sum())
+        t0 = time.perf_counter()
+        st = R.run(st, "cpf2", op, steps - 250)
+        samples = []
+        for _ in range(10):
+            st = R.run(st, "cpf2", op, 25)
+            samples.append(R.laplace_sigma(R.moments(st, "cpf2", op), op))
+        el = time.perf_counter() - t0
+    finally:
+        torch.set_num_threads(prev)
+    m = R.moments(st, "cpf2", op)
+    sig = sum(v[0] for v in samples) / len(samples)
+    rn = samples[-1][1]
+    return {"workload": "64x64 droplet, R=16, W=4, density ratio 10, sigma=0.01, tau_f=tau_h=0.8, CPF-2, FP64",
+            "steps": steps, "seconds": round(el, 2), "cores": threads,
+            "note": "seconds include the ten Laplace samples (moments) of the last 250 steps",
+            "MLUPS": round(64 * 64 * steps / el / 1e6, 3),
+            "laplace_sigma_num": round(sig, 6), "laplace_rel_error": round(abs(sig - op.sigma) / op.sigma, 4),
+            "R_num": round(rn, 3), "phi_sum_drift": float(m["phi"].sum()) - s0}
 
 
 def bench_batched(steps, loop_steps):

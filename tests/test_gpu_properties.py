@@ -236,3 +236,40 @@ def test_step_blobs_equals_restore_step_save(case):
     r2 = sim.save()
     torch.cuda.synchronize()
     assert torch.equal(b1, r1) and torch.equal(b2, r2)
+
+
+def test_full_size_channel_bubble_rises_50000_steps():
+    """The 1024x4096 channel (no-slip x walls, periodic y) with a bubble of
+    R = 128 at y = 512, Eo = 10, Mo = 1e-3, STF-2, for 50000 steps: the launch
+    shape of the full-size run, checked through properties that hold at any
+    size.  At density ratio 1000 the method diverges within 5000 steps here
+    (and a stationary gas bubble at that ratio diverges in the oracle too), so
+    the run uses the density and viscosity ratios 10 of the paper's own
+    rising bubble (Table IV), W = 4 and Pe = 1/Cn (Sec. V), U_g = 0.01,
+    tau_h = 4.  The order parameter is conserved, the bubble rises every
+    5000 steps and reaches a steady rise velocity, and it stays round to
+    within its deformation at this Eotvos number."""
+    import paper_2012_14729_amd as P
+    from paper_2012_14729_amd.diagnostics import bubble_metrics
+    from paper_2012_14729_amd.units import Groups, lattice_params
+    L, W = 256.0, 4.0
+    g = Groups(Re=(10.0 ** 3 / 1e-3) ** 0.25, We=10.0, Pe=L / W, Cn=W / L, Fr=1.0, rho_ratio=0.1, mu_ratio=0.1)
+    d = lattice_params(g, L_c=L, U_c=0.01, tau_h=4.0, nx=1024, ny=4096, wall_x=1)
+    phi0 = np.asarray(WL.droplet(1024, 4096, 128.0, W, xc=512.0, yc=512.0, inside=-1.0), np.float32)
+    s = P.Simulation(d, phi0)
+    mass0 = float(s.moments("stf2")["phi"].double().sum())
+    hist = []
+    for k in range(10):
+        s.step(5000, "stf2")
+        m = s.moments("stf2")
+        assert not s.status(), f"diverged by step {(k + 1) * 5000}"
+        yc, vc, C = bubble_metrics(m["phi"], m["uy"])
+        hist.append((yc, vc, C))
+        print(f"[channel] step {(k + 1) * 5000}: y_c {yc:.1f} v_c {vc:.3e} C {C:.3f}", flush=True)
+    dm = abs(float(m["phi"].double().sum()) - mass0) / (1024 * 4096)
+    assert dm < 1e-9, dm
+    ys = [h[0] for h in hist]
+    assert all(b > a for a, b in zip([512.0] + ys, ys))
+    assert ys[-1] < 4096 - 256
+    assert abs(hist[-1][1] - hist[-2][1]) < 0.02 * hist[-1][1]   # steady rise velocity
+    assert 0.85 < hist[-1][2] <= 1.0
