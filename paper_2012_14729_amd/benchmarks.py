@@ -66,12 +66,14 @@ def bubble_params(res: int, U_g: float = 0.05, W: float = 4.0, M: Optional[float
 
 
 def shear_drop(form: str, Ca: float, R: float = 20.0, H: float = 160.0, nu: float = 1.0 / 6.0, Re: float = 0.1,
-               W: float = 4.0, M: float = 0.1, shear_times: float = 3.0, samples: int = 6):
+               W: float = 4.0, M: Optional[float] = None, shear_times: float = 3.0, samples: int = 6,
+               rho_ratio: float = 1.0, tau_h: float = 0.8, Pe: Optional[float] = None):
     """Run the sheared drop for `shear_times` / E steps; returns a dict with
     the history [(step, D)], the last D, L, B and the drop area.  The run
     starts from the circular drop in the Couette profile."""
     nx, ny = int(round(2 * H)), int(round(H))
-    p = shear_drop_params(R=R, H=H, Re=Re, Ca=Ca, nu=nu, W=W, M=M, nx=nx, ny=ny)
+    p = shear_drop_params(R=R, H=H, Re=Re, Ca=Ca, nu=nu, W=W, M=M, tau_h=tau_h, rho_ratio=rho_ratio, Pe=Pe,
+                          nx=nx, ny=ny)
     E = Re * nu / (R * R)
     U = p["u_wall_hi"]
     x = np.arange(nx, dtype=np.float64)[None, :].repeat(ny, 0)
@@ -91,7 +93,7 @@ def shear_drop(form: str, Ca: float, R: float = 20.0, H: float = 160.0, nu: floa
     torch.cuda.synchronize()
     return dict(form=form, Ca=Ca, history=hist, D=hist[-1][1], L=L, B=B, area=area, steps=total,
                 shear_time=total * E, seconds=time.time() - t0, diverged=sim.status(),
-                theory=taylor_theory(Ca, 1.0), nodes=nx * ny)
+                theory=taylor_theory(Ca, rho_ratio), nodes=nx * ny, M=p["M"])
 
 
 def rising_bubble(form: str, res: int = 240, U_g: float = 0.05, W: float = 4.0,
@@ -237,9 +239,10 @@ def _main():
         return
     for Ca in [float(v) for v in a.ca.split(",")]:
         for form in a.forms.split(","):
-            r = shear_drop(form, Ca, R=a.R, H=8 * a.R, M=0.1 if a.M is None else a.M, shear_times=a.shear_times)
+            r = shear_drop(form, Ca, R=a.R, H=8 * a.R, M=a.M, shear_times=a.shear_times, rho_ratio=a.rho_ratio,
+                           tau_h=0.8 if a.tau_h is None else a.tau_h)
             h = r["history"]
-            print(f"taylor form={form} Ca={Ca} R={a.R:g} M={0.1 if a.M is None else a.M:g} D={r['D']:.4f} dD_last={h[-1][1] - h[-2][1]:+.4f} "
+            print(f"taylor form={form} Ca={Ca} R={a.R:g} rho_d/rho_s={a.rho_ratio:g} M={r['M']:.4g} D={r['D']:.4f} dD_last={h[-1][1] - h[-2][1]:+.4f} "
                   f"theory={r['theory']:.4f} steps={r['steps']} tE={r['shear_time']:.2f} area={r['area']:.0f} "
                   f"MLUPS={r['nodes'] * r['steps'] / r['seconds'] / 1e6:.0f} diverged={r['diverged']}", flush=True)
 

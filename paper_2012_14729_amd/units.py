@@ -98,17 +98,26 @@ def rising_bubble_params(R: float, Eo: float, Mo: float, U_g: float = 0.01, rho1
     return out
 
 
-def shear_drop_params(R: float, H: float, Re: float, Ca: float, nu: float = 0.1, W: float = 4.0, M: float = 0.1,
-                      tau_h: float = 0.8, **extra) -> dict:
+def shear_drop_params(R: float, H: float, Re: float, Ca: float, nu: float = 0.1, W: float = 4.0,
+                      M: Optional[float] = 0.1, tau_h: float = 0.8, rho_ratio: float = 1.0, Pe: Optional[float] = None,
+                      **extra) -> dict:
     """Lattice parameters of a drop of radius R in a channel of height H
-    (nodes) sheared by walls at +-U (Sec. V.E), equal densities and
-    viscosities: E = Re nu / R^2, U = E H / 2, sigma = mu E R / Ca.  The wall
-    speeds go to u_wall_lo = -U, u_wall_hi = +U (walls in y)."""
+    (nodes) sheared by walls at +-U (Sec. V.E): the drop (fluid 1) has
+    density rho_ratio, the surrounding fluid density 1, both kinematic
+    viscosity nu (so the viscosity ratio is rho_ratio too); E = Re nu / R^2
+    (Re = E rho_d R^2 / mu_d), U = E H / 2, sigma = mu_s E R / Ca with the
+    surrounding fluid's viscosity, the one small-deformation theory puts in
+    Ca.  M = None takes the mobility from Pe (default 1/Cn) with L_c = R and
+    U_c = E R: M = E R^2 / (4 beta Pe), Cn = W / R.  The wall speeds go to
+    u_wall_lo = -U, u_wall_hi = +U (walls in y)."""
     E = Re * nu / (R * R)
     U = E * H / 2.0
     sigma = nu * E * R / Ca
-    out = dict(wall_y=1, u_wall_lo=-U, u_wall_hi=U, rho1=1.0, rho2=1.0, nu1=nu, nu2=nu, sigma=sigma, W=W, M=M,
-               tau_h=tau_h)
+    if M is None:
+        beta = 3.0 * sigma / (4.0 * W)
+        M = E * R * R / (4.0 * beta * ((R / W) if Pe is None else Pe))
+    out = dict(wall_y=1, u_wall_lo=-U, u_wall_hi=U, rho1=rho_ratio, rho2=1.0, nu1=nu, nu2=nu, sigma=sigma, W=W,
+               M=M, tau_h=tau_h)
     out.update(extra)
     return out
 

@@ -71,10 +71,29 @@ def test_shear_recipe_matches_shear_workload():
 
 
 def test_taylor_deformation_matches_printed_theory_row():
-    """Table VI, row 'Eq. (52)': viscosity ratio 1 at Ca = 0.1..0.4."""
+    """Table VI, row 'Eq. (52)': viscosity ratio 1 at Ca = 0.1..0.4, and 0.1
+    (the drop/surrounding density ratio 0.1 at equal kinematic viscosity)
+    at Ca = 0.1..0.3."""
     tab = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table6_taylor.json")))
     for ca, d in zip(tab["Ca"], tab["theory_rho1"]):
         assert abs(U.taylor_deformation(ca, 1.0) - d) < 6e-5, (ca, d)
+    for ca, d in zip(tab["Ca_rho01"], tab["theory_rho01"]):
+        assert abs(U.taylor_deformation(ca, 0.1) - d) < 6e-5, (ca, d)
+
+
+def test_shear_drop_parameters_follow_the_paper_recipe():
+    """Sec. V.E: Re = E rho_d R^2 / mu_d = 0.1, Ca = mu_s E R / sigma, the drop
+    at density rho_ratio with the surrounding fluid's kinematic viscosity, and
+    Pe = 1/Cn with L_c = R, U_c = E R: M = E R^2 / (4 beta Pe)."""
+    R, H, nu = 20.0, 160.0, 1.0 / 6.0
+    for rr in (1.0, 0.1):
+        p = U.shear_drop_params(R=R, H=H, Re=0.1, Ca=0.2, nu=nu, W=4.0, M=None, rho_ratio=rr)
+        E = 2.0 * p["u_wall_hi"] / H
+        assert math.isclose(E * p["rho1"] * R * R / (p["rho1"] * p["nu1"]), 0.1)
+        assert math.isclose(p["rho2"] * p["nu2"] * E * R / p["sigma"], 0.2)
+        assert math.isclose(p["rho1"] / p["rho2"], rr) and math.isclose(p["nu1"], p["nu2"])
+        beta = 3.0 * p["sigma"] / (4.0 * p["W"])
+        assert math.isclose(E * R * R / (4.0 * p["M"] * beta), R / p["W"])
 
 
 def test_capillary_wave_parameters_follow_the_paper_recipe():
