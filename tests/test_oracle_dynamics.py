@@ -175,14 +175,21 @@ def test_flat_interface_is_stationary(form):
 def test_laplace_law(form):
     """Stationary droplet (Sec. V.A): sigma_num = R_num (p_in - p_out) lies
     within the error band the paper prints in Table I for W = 4 and R of
-    about 15 cells (largest error there: PF-2, 7.9%)."""
+    about 15 cells (largest error there: PF-2, 7.9%).  The pressure still
+    rings acoustically (period about 75 steps) after 900 steps, so sigma_num
+    is the mean of twelve samples 25 steps apart (four periods)."""
     import json, os
     tab = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table1_laplace.json")))
     band = max(max(v) for v in tab["err_percent"].values()) / 100.0
     n, r = 64, 16.0
     p = R.Params(nx=n, ny=n, rho1=10.0, rho2=1.0, nu1=1 / 6, nu2=1 / 6, sigma=0.01, W=4.0, M=0.1)
-    st = R.run(R.init(p, drop(n, n, r, 4.0, n / 2, n / 2)), form, p, 3000)
-    sig, rn = R.laplace_sigma(R.moments(st, form, p), p)
+    st = R.run(R.init(p, drop(n, n, r, 4.0, n / 2, n / 2)), form, p, 900)
+    samples = []
+    for _ in range(12):
+        st = R.run(st, form, p, 25)
+        samples.append(R.laplace_sigma(R.moments(st, form, p), p))
+    sig = sum(v[0] for v in samples) / len(samples)
+    rn = samples[-1][1]
     assert abs(rn - r) < 0.5
     assert abs(sig - p.sigma) / p.sigma < band, sig
 
