@@ -378,9 +378,11 @@ def main():
     torch.cuda.synchronize()
     print("[bench] warm-up done", file=sys.stderr, flush=True)
 
-    # The launch durations are sampled on one step in `period`: events around
-    # every launch would add their own gaps to the timed region.  A period no
-    # longer than the shortest run times at least one step of every run.
+    # The launch durations are sampled on one step in `period` of each run,
+    # its first step included: events around every launch would add their
+    # own gaps to the timed region.  A run's first step is slower than the
+    # rest (the previous run's state, not this one's, sits in the caches),
+    # so a period no longer than the shortest run also samples later steps.
     timed = [(f, sims[f], n) for f, n in zip(FORMS, counts) if n > 0]
     period = min([TIMING_PERIOD] + [n for _, _, n in timed])
     for _, s, _ in timed:

@@ -162,8 +162,8 @@ int lbm_step_blobs(lbm_sim* sim, const void* d_blob_in, void* d_blob_out, int32_
 
 /* Kernel timing with HIP events recorded on the launch stream around the
  * launches of one kernel.  period: 0 = off; k >= 1 = time the two launches of
- * every k-th step (step counter divisible by k), so k > 1 samples the launch
- * durations with fewer events in the stream.  kernel: 0 = fused
+ * every k-th step counted from this call, the first step after it included,
+ * so k > 1 samples the launch durations with fewer events in the stream.  kernel: 0 = fused
  * collide-stream kernel, 1 = order parameter kernel.  lbm_kernel_time
  * synchronises and returns the summed elapsed milliseconds and the number of
  * timed launches since the last reset; every call of lbm_set_timing drains

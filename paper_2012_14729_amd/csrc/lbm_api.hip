@@ -168,6 +168,7 @@ struct lbm_sim {
   int shape;        // tile shape of the step kernels (index into kShapeTX/kShapeTY)
   int64_t step;
   int timing;
+  int64_t timing_base;   // step count when timing was last set: the first step after it is timed
   // ring of event pairs per kernel: [kernel][slot][start/stop]; a slot is
   // drained (its elapsed time added) before reuse or on query
   static constexpr int kRing = 512;
@@ -319,7 +320,7 @@ int lbm_step(lbm_sim* s, int32_t nsteps, int32_t form, void* stream) {
   for (int32_t n = 0; n < nsteps; ++n) {
     StepArgs a = step_args(s);
     int slot = 0;
-    const bool timed = s->timing && s->step % s->timing == 0;
+    const bool timed = s->timing && (s->step - s->timing_base) % s->timing == 0;
     if (timed)
       if (int r = timer_start(s, 0, st, &slot)) return r;
     HIPCHK(launch_fused(form, s->shape, a, st));
@@ -434,7 +435,8 @@ int lbm_set_timing(lbm_sim* s, int32_t enable) {
   for (int k = 0; k < 2; ++k)
     if (s->ev[0][0][0])
       if (int r = drain_all(s, k)) return r;
-  s->timing = enable;   // 0: off; k: every k-th step
+  s->timing = enable;   // 0: off; k: every k-th step, starting with the next one
+  s->timing_base = s->step;
   s->t_ms[0] = s->t_ms[1] = 0.0;
   s->t_n[0] = s->t_n[1] = 0;
   return LBM_OK;

@@ -98,6 +98,13 @@ def test_zero_steps_and_timing():
     ms1, n1 = s.kernel_time(1)
     assert n1 == 7 and ms1 > 0
     assert s.step_count == 7
+    # a period counts from the set_timing call, its first step included
+    s.set_timing(True, period=4)
+    s.step(5, "cpf2")
+    assert s.kernel_time(0)[1] == 2 and s.kernel_time(1)[1] == 2
+    s.set_timing(True, period=8)
+    s.step(3, "cpf2")
+    assert s.kernel_time(0)[1] == 1
 
 
 def _one_step_full_size(p, phi0, form):
