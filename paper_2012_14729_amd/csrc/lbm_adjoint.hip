@@ -288,13 +288,18 @@ constexpr int kH3W = AS::TX + 6, kH3H = AS::TY + 6;   // halo 3
 constexpr int kH2W = AS::TX + 4, kH2H = AS::TY + 4;   // halo 2
 constexpr int kH1W = AS::TX + 2, kH1H = AS::TY + 2;   // halo 1
 
+// ld lives in phases 0-1 and la in phases 3-4, so they share storage: the
+// window then takes 51 KB, and two workgroups leave room on a CU for a
+// 512-thread step kernel from another stream (the overlapped recompute).
 struct AdjLds {
   double phi[kH4H][kH4W];       // phi extended (wrap / even reflection)
   double gl[3][kH3H][kH3W];     // grad phi (x, y), lap phi
-  double ld[kH3H][kH3W];        // adjoint of D = div(phi u) at nodes (0 beyond walls)
+  union {
+    double ld[kH3H][kH3W];      // adjoint of D = div(phi u) at nodes (0 beyond walls)
+    double la[4][kH1H][kH1W];   // adjoints of grad phi (2), lap phi, and the phi part of mu_phi
+  };
   double lq[2][kH3H][kH3W];     // adjoint of the extended node field phi u, from div
   double lf[3][kH2H][kH2W];     // adjoint of F_sf at nodes (2) and, for CSF, of div n
-  double la[4][kH1H][kH1W];     // adjoints of grad phi (2), lap phi, and the phi part of mu_phi
   double lp[kH2H][kH2W];        // adjoint of the extended phi from the stencils and mu_phi
   double red[kAT / 64];
 };
