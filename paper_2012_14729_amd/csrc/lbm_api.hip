@@ -169,12 +169,14 @@ struct lbm_sim {
   int64_t step;
   int timing;
   int64_t timing_base;   // step count when timing was last set: the first step after it is timed
-  // ring of event pairs per kernel: [kernel][slot][start/stop]; a slot is
-  // drained (its elapsed time added) before reuse or on query
+  // ring of event triples, one per timed step: before the fused kernel,
+  // between the two kernels (the fused kernel's stop and the order-parameter
+  // kernel's start), after the order-parameter kernel; a slot is drained
+  // (its elapsed times added) before reuse or on query
   static constexpr int kRing = 512;
-  hipEvent_t ev[2][kRing][2];
-  int ev_pending[2][kRing];
-  int ev_next[2];
+  hipEvent_t ev[kRing][3];
+  int ev_pending[kRing];
+  int ev_next;
   double t_ms[2];
   int64_t t_n[2];
   float* S(int b) const { return (float*)(ws + L.off_s[b]); }
@@ -197,36 +199,36 @@ StepArgs step_args(const lbm_sim* s) {
 }
 
 // Add the elapsed time of ring slot `j` of kernel `k` if it holds a launch.
-int drain_slot(lbm_sim* s, int k, int j) {
-  if (!s->ev_pending[k][j]) return LBM_OK;
-  HIPCHK(hipEventSynchronize(s->ev[k][j][1]));
-  float ms = 0.f;
-  HIPCHK(hipEventElapsedTime(&ms, s->ev[k][j][0], s->ev[k][j][1]));
-  s->t_ms[k] += ms;
-  s->t_n[k] += 1;
-  s->ev_pending[k][j] = 0;
+int drain_slot(lbm_sim* s, int j) {
+  if (!s->ev_pending[j]) return LBM_OK;
+  HIPCHK(hipEventSynchronize(s->ev[j][2]));
+  for (int k = 0; k < 2; ++k) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, s->ev[j][k], s->ev[j][k + 1]));
+    s->t_ms[k] += ms;
+    s->t_n[k] += 1;
+  }
+  s->ev_pending[j] = 0;
   return LBM_OK;
 }
 
-int drain_all(lbm_sim* s, int k) {
+int drain_all(lbm_sim* s) {
   for (int j = 0; j < lbm_sim::kRing; ++j)
-    if (int r = drain_slot(s, k, j)) return r;
+    if (int r = drain_slot(s, j)) return r;
   return LBM_OK;
 }
 
-// Record the start event of kernel k's next timed launch; returns the slot.
-int timer_start(lbm_sim* s, int k, hipStream_t st, int* slot) {
-  const int j = s->ev_next[k];
-  s->ev_next[k] = (j + 1) % lbm_sim::kRing;
-  if (int r = drain_slot(s, k, j)) return r;
-  HIPCHK(hipEventRecord(s->ev[k][j][0], st));
-  *slot = j;
-  return LBM_OK;
-}
-
-int timer_stop(lbm_sim* s, int k, int j, hipStream_t st) {
-  HIPCHK(hipEventRecord(s->ev[k][j][1], st));
-  s->ev_pending[k][j] = 1;
+// Event e (0: before the fused kernel, 1: between the kernels, 2: after the
+// order-parameter kernel) of the timed step in slot j; e = 0 takes a new slot.
+int timer_mark(lbm_sim* s, int e, hipStream_t st, int* slot) {
+  if (e == 0) {
+    const int j = s->ev_next;
+    s->ev_next = (j + 1) % lbm_sim::kRing;
+    if (int r = drain_slot(s, j)) return r;
+    *slot = j;
+  }
+  HIPCHK(hipEventRecord(s->ev[*slot][e], st));
+  if (e == 2) s->ev_pending[*slot] = 1;
   return LBM_OK;
 }
 
@@ -322,15 +324,13 @@ int lbm_step(lbm_sim* s, int32_t nsteps, int32_t form, void* stream) {
     int slot = 0;
     const bool timed = s->timing && (s->step - s->timing_base) % s->timing == 0;
     if (timed)
-      if (int r = timer_start(s, 0, st, &slot)) return r;
+      if (int r = timer_mark(s, 0, st, &slot)) return r;
     HIPCHK(launch_fused(form, s->shape, a, st));
-    if (timed) {
-      if (int r = timer_stop(s, 0, slot, st)) return r;
-      if (int r = timer_start(s, 1, st, &slot)) return r;
-    }
+    if (timed)
+      if (int r = timer_mark(s, 1, st, &slot)) return r;
     HIPCHK(launch_phi(a.sout, s->phi(), s->phi(), s->L.g, s->c.wall_x, s->c.wall_y, s->shape, st));
     if (timed)
-      if (int r = timer_stop(s, 1, slot, st)) return r;
+      if (int r = timer_mark(s, 2, st, &slot)) return r;
     s->cur = 1 - s->cur;
     s->step += 1;
   }
@@ -427,14 +427,12 @@ int lbm_step_blobs(lbm_sim* s, const void* d_blob_in, void* d_blob_out, int32_t 
 int lbm_set_timing(lbm_sim* s, int32_t enable) {
   if (!s) return fail(LBM_E_INVAL, "sim is NULL");
   if (enable < 0) return fail(LBM_E_INVAL, "timing period must be >= 0");
-  if (enable && !s->ev[0][0][0]) {   // create the event ring on first use
-    for (int k = 0; k < 2; ++k)
-      for (int j = 0; j < lbm_sim::kRing; ++j)
-        for (int e = 0; e < 2; ++e) HIPCHK(hipEventCreate(&s->ev[k][j][e]));
+  if (enable && !s->ev[0][0]) {   // create the event ring on first use
+    for (int j = 0; j < lbm_sim::kRing; ++j)
+      for (int e = 0; e < 3; ++e) HIPCHK(hipEventCreate(&s->ev[j][e]));
   }
-  for (int k = 0; k < 2; ++k)
-    if (s->ev[0][0][0])
-      if (int r = drain_all(s, k)) return r;
+  if (s->ev[0][0])
+    if (int r = drain_all(s)) return r;
   s->timing = enable;   // 0: off; k: every k-th step, starting with the next one
   s->timing_base = s->step;
   s->t_ms[0] = s->t_ms[1] = 0.0;
@@ -444,8 +442,8 @@ int lbm_set_timing(lbm_sim* s, int32_t enable) {
 
 int lbm_kernel_time(lbm_sim* s, int32_t kernel, double* total_ms, int64_t* launches) {
   if (!s || !total_ms || !launches || kernel < 0 || kernel > 1) return fail(LBM_E_INVAL, "bad argument");
-  if (s->ev[0][0][0])
-    if (int r = drain_all(s, kernel)) return r;
+  if (s->ev[0][0])
+    if (int r = drain_all(s)) return r;
   *total_ms = s->t_ms[kernel];
   *launches = s->t_n[kernel];
   return LBM_OK;
@@ -453,10 +451,9 @@ int lbm_kernel_time(lbm_sim* s, int32_t kernel, double* total_ms, int64_t* launc
 
 int lbm_destroy(lbm_sim* s) {
   if (!s) return LBM_OK;
-  for (int k = 0; k < 2; ++k)
-    for (int j = 0; j < lbm_sim::kRing; ++j)
-      for (int e = 0; e < 2; ++e)
-        if (s->ev[k][j][e]) (void)hipEventDestroy(s->ev[k][j][e]);
+  for (int j = 0; j < lbm_sim::kRing; ++j)
+    for (int e = 0; e < 3; ++e)
+      if (s->ev[j][e]) (void)hipEventDestroy(s->ev[j][e]);
   delete s;
   return LBM_OK;
 }
