@@ -769,7 +769,7 @@ __global__ __launch_bounds__(kB) void k_sum_part(const double* __restrict__ a, l
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = kB / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
@@ -782,7 +782,7 @@ __global__ __launch_bounds__(kB) void k_sum_fin(const double* __restrict__ part,
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = kB / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = red[0];
