@@ -35,10 +35,10 @@ HBM_PEAK_GBS = 8000.0
 # the 9 f and 9 h populations (144 B), read and write the (phi u) history
 # (16 B), read phi (4 B) = 164 B.
 BYTES_FUSED_ALG = 9 * 4 * 2 + 9 * 4 * 2 + 2 * 4 * 2 + 4
-# What this design's fused kernel moves per node (FP32 populations, FP32
-# pressure plane, FP64 phi): read 9 f + P + 8 h (pulled) + 2 J + phi (8 B);
-# write 9 f + P + 8 h + d0 + 2 J.
-BYTES_FUSED = 9 * 4 + 4 + 8 * 4 + 2 * 4 + 8 + 9 * 4 + 4 + 9 * 4 + 2 * 4
+# What this design's fused kernel moves per node (FP32 populations, FP64
+# phi): read 9 f + 8 h (pulled; d0 is read by the order-parameter kernel) +
+# 2 J + phi (8 B); write 9 f + 8 h + d0 + 2 J.  The same 164 B.
+BYTES_FUSED = 9 * 4 + 8 * 4 + 2 * 4 + 8 + 9 * 4 + 9 * 4 + 2 * 4
 #   order-parameter kernel: read d0 + 8 h (pulled) + phi (8 B); write phi (8 B)
 BYTES_PHI = 4 + 8 * 4 + 8 + 8
 FORMS = ("stf1", "stf2", "cpf1", "cpf2", "pf1", "pf2", "csf1", "csf2")
@@ -428,7 +428,7 @@ def main():
                 "timed_launches": fused_n,
                 "design_basis": {"bytes_per_node": BYTES_FUSED, "achieved": round(achieved_design, 1),
                                  "frac": round(achieved_design / HBM_PEAK_GBS, 4),
-                                 "note": "adds the FP32 pressure plane (read+write) and phi in FP64"},
+                                 "note": "8 pulled h (d0 goes to the order-parameter kernel) and phi in FP64: the same total"},
                 "phi_kernel": {"avg_launch_us": round(phi_avg_s * 1e6, 2),
                                "achieved_GBs": round(BYTES_PHI * cells / phi_avg_s / 1e9, 1),
                                "bytes_per_node": BYTES_PHI}}

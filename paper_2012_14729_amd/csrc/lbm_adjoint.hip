@@ -145,8 +145,8 @@ __global__ __launch_bounds__(kAT) void k_adj_a(AArgs A) {
   double dM = 0.0;
   if (act) {
     const int N = A.nx * A.ny, k = y * A.nx + x;
-    float ft[9], ps[9];
-    load_fp<WX, WY>(a, x, y, ft, ps);
+    float ft[9];
+    load_fp<WX, WY>(a, x, y, ft);
     // lambda_{n+1} along the streamed links: the post-collision value of
     // direction i at x became population i at x + c_i, or population opp(i)
     // at x where x + c_i lies beyond a wall (Eq. 43)
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(kAT) void k_adj_a(AArgs A) {
     double fv[9], jx = 0.0, jy = 0.0, S = 0.0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      fv[i] = (double)ft[i] + wtd(i) * (double)ps[i];
+      fv[i] = (double)ft[i];
       jx += cx(i) * fv[i];
       jy += cy(i) * fv[i];
       S += fv[i];

@@ -4,14 +4,13 @@
 // it), stored as constexpr functions so fully unrolled loops fold them into
 // immediates.  Device state of one lattice (x fastest, pitch = nx rounded up
 // to 64):
-//   S[2]  FP32 ping-pong state arrays of 21 planes, interleaved in row
+//   S[2]  FP32 ping-pong state arrays of 20 planes, interleaved in row
 //         segments of 64 nodes: element (plane p, x, y) lies at
-//         ((y * ncx + x / 64) * 21 + p) * 64 + x % 64  (ncx = pitch / 64), so
-//         the 21 values of a 64-node row segment are one 5376-byte run.
-//         planes 0-8   f_i - w_i P of the storing node (post-collision)
+//         ((y * ncx + x / 64) * 20 + p) * 64 + x % 64  (ncx = pitch / 64), so
+//         the 20 values of a 64-node row segment are one 5120-byte run.
+//         planes 0-8   f_i (post-collision)
 //         planes 9-17  h_i (post-collision); plane 9 holds d0 = h_0^+ - phi
-//         plane 18     P_sf of the storing node
-//         planes 19-20 (phi u) of the step that stored them
+//         planes 18-19 (phi u) of the step that stored them
 //   phi   FP64 plane (pitch * ny), updated in place
 #pragma once
 
@@ -32,8 +31,8 @@ __host__ __device__ constexpr int dir_of(int x, int y) {
 __host__ __device__ constexpr int mirror_x(int i) { return dir_of(-cx(i), cy(i)); }
 __host__ __device__ constexpr int mirror_y(int i) { return dir_of(cx(i), -cy(i)); }
 
-constexpr int kNPL = 21;  // planes of a state array
-constexpr int kPF = 0, kPH = 9, kPP = 18, kPJ = 19;   // first plane of f, h, P, J
+constexpr int kNPL = 20;  // planes of a state array
+constexpr int kPF = 0, kPH = 9, kPJ = 18;   // first plane of f, h, J
 constexpr int kSegE = kNPL * 64;   // elements of one interleaved row segment
 
 // Tile shapes of the fused and order-parameter kernels (TX x TY nodes, one
@@ -65,7 +64,7 @@ struct Grid {
   int nx, ny, pitch;
   int ncx;                // 64-node row segments per row (pitch / 64)
   long long ps;           // nodes of a padded plane (pitch * ny)
-  int rowe;               // elements of one row of a state array (ncx * 21 * 64)
+  int rowe;               // elements of one row of a state array (ncx * 20 * 64)
   int fast;               // addressing paths allowed (kFastInterior | kFastWrap)
   int slip_x, slip_y;     // the walls of that axis are free-slip (specular), not no-slip
 };
@@ -79,7 +78,7 @@ __host__ __device__ constexpr int fast_bits(long long plane_nodes) {
   return kFastInterior | ((long long)kNPL * plane_nodes * 4 <= 0xffffffffLL ? kFastWrap : 0);
 }
 
-// Element index of plane 0 of node (x, y) in a state array (21 ps < 2^32 is
+// Element index of plane 0 of node (x, y) in a state array (20 ps < 2^32 is
 // validated); plane p of the node is 64 p elements further.
 __host__ __device__ __forceinline__ unsigned nbase(const Grid& g, int x, int y) {
   return (unsigned)(y * g.ncx + (x >> 6)) * (unsigned)kSegE + (unsigned)(x & 63);

@@ -13,7 +13,7 @@
 // halo (FP64); second-level stencil fields live on the 2-node ring, the
 // velocity on the 1-node ring.  Only nearest-neighbour pulls touch
 // HBM; everything with a wider footprint comes from LDS.  The state arrays
-// interleave their 21 planes in 64-node row segments (lbm_internal.hpp), so a
+// interleave their 20 planes in 64-node row segments (lbm_internal.hpp), so a
 // wavefront's loads and stores of one row segment form one contiguous run.
 #include "lbm_tile.hpp"
 
@@ -38,7 +38,7 @@ __global__ __launch_bounds__(S::NT) void k_phi(const float* __restrict__ snew, c
 
 // Initial state, pass 1: node-local f^eq(P = 0, rho(phi0), u0) and
 // h^eq(phi0, mu(phi0), u0) (Eqs. 31-32; reading A11) into the f and h planes
-// of s_tmp; phi (FP64); P = 0 and (phi u) = phi0 u0 into s0.
+// of s_tmp; phi (FP64); (phi u) = phi0 u0 into s0.
 __global__ __launch_bounds__(256) void k_init_local(const float* __restrict__ phi0, const float* __restrict__ ux0,
                                                     const float* __restrict__ uy0, float* __restrict__ s_tmp,
                                                     float* __restrict__ s0, double* __restrict__ phi, Grid g, Phys c) {
@@ -78,7 +78,6 @@ __global__ __launch_bounds__(256) void k_init_local(const float* __restrict__ ph
     s_tmp[on + (unsigned)((kPH + i) * 64)] = (i == 0) ? 0.0f : wt(i) * etamu + wt(i) * (float)p0 * 3.0f * cu;
   }
   phi[(long long)y * g.pitch + x] = p0;
-  s0[on + (unsigned)(kPP * 64)] = 0.0f;   // P0 = 0: the stored f are then f itself
   s0[on + (unsigned)(kPJ * 64)] = (float)p0 * ux;
   s0[on + (unsigned)((kPJ + 1) * 64)] = (float)p0 * uy;
 }

@@ -95,8 +95,7 @@ __device__ __forceinline__ unsigned src_base(int x, int y, const Grid& g, int wx
 // so a load or store is one SGPR-base + VGPR-offset + immediate access with
 // no vector address arithmetic.  Values used once (a node's own pulled
 // populations and (phi u), every store) go through the non-temporal path;
-// the source pressures and the ring's pulls, which neighbours read again,
-// do not.
+// the ring's pulls, which the neighbouring tile reads again, do not.
 template <class T>
 __device__ __forceinline__ const T* at(const T* base, unsigned boff) {
   return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + boff);
@@ -295,37 +294,33 @@ __device__ __forceinline__ void force_sf(const Lds<S>& s, int uy_, int ux_, cons
 }
 
 // Everything the collision of an active node needs (FP64 arithmetic, FP32
-// storage).  The flow populations are kept relative to the node's new
-// pressure: f[i] = f_i - w_i Pn.
+// storage): the pulled flow populations and the node's moments.
 struct NodeState {
   float f[9];
-  float Pn, fx, fy, grx, gry, mu;
+  float fx, fy, grx, gry, mu;
   double ux, uy, rho, P;
 };
 
-// Pull the stored flow populations and the pressures of their source nodes
-// for node (x, y) inside the domain (Eqs. 29 and 43, pull form).
+// Pull the stored flow populations for node (x, y) inside the domain
+// (Eqs. 29 and 43, pull form).
 template <bool WX, bool WY>
-__device__ __forceinline__ void load_fp(const StepArgs& a, int x, int y, float* ft, float* ps) {
+__device__ __forceinline__ void load_fp(const StepArgs& a, int x, int y, float* ft) {
   constexpr int wx = WX, wy = WY;
 #define PULL_FP(I)                                               \
   {                                                              \
     int sl_;                                                     \
     const unsigned b_ = src_base<I>(x, y, a.g, wx, wy, sl_);     \
     ft[I] = a.sin[b_ + (unsigned)((kPF + sl_) * 64)];            \
-    ps[I] = a.sin[b_ + (unsigned)(kPP * 64)];                    \
   }
   PULL_FP(0) PULL_FP(1) PULL_FP(2) PULL_FP(3) PULL_FP(4) PULL_FP(5) PULL_FP(6) PULL_FP(7) PULL_FP(8)
 #undef PULL_FP
 }
 
 // Velocity (and, for active nodes, the rest of Eq. 37) at a node whose
-// velocity-ring position is (uy_, ux_).  The stored flow populations are
-// deviations from the pressure of the node that stored them:
-// f_i = ft_i + w_i ps_i.
+// velocity-ring position is (uy_, ux_), from its pulled flow populations ft.
 template <int FORM, bool FULL, class S>
 __device__ __forceinline__ void velocity_from(const Lds<S>& s, const StepArgs& a, int uy_, int ux_, const float* ft,
-                                              const float* ps, NodeState& ns) {
+                                              NodeState& ns) {
   double fx, fy;
   force_sf<FORM, S>(s, uy_, ux_, a.c, fx, fy);
   const double phid = s.phi[uy_ + 2][ux_ + 2];
@@ -335,7 +330,7 @@ __device__ __forceinline__ void velocity_from(const Lds<S>& s, const StepArgs& a
   double jx = 0.0, jy = 0.0;
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
-    const double fi = (double)ft[i] + wtd(i) * (double)ps[i];
+    const double fi = (double)ft[i];
     if (cx(i) != 0) jx += cx(i) * fi;
     if (cy(i) != 0) jy += cy(i) * fi;
   }
@@ -355,13 +350,10 @@ __device__ __forceinline__ void velocity_from(const Lds<S>& s, const StepArgs& a
     ns.mu = (float)chem_pot(phid, lap, a.c);
     double sumf = 0.0;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) sumf += (double)ft[i] + wtd(i) * (double)ps[i];
-    const double P = sumf + (ux * grx + uy * gry) * (0.5 / 3.0);   // Eq. (37)
-    const float Pn = (float)P;
-    ns.P = P;
-    ns.Pn = Pn;
+    for (int i = 0; i < 9; ++i) sumf += (double)ft[i];
+    ns.P = sumf + (ux * grx + uy * gry) * (0.5 / 3.0);   // Eq. (37)
 #pragma unroll
-    for (int i = 0; i < 9; ++i) ns.f[i] = (float)((double)ft[i] + wtd(i) * ((double)ps[i] - (double)Pn));
+    for (int i = 0; i < 9; ++i) ns.f[i] = ft[i];
   }
 }
 
@@ -437,13 +429,11 @@ __device__ __forceinline__ float dotcf(int i, float vx, float vy) {
   return tx + ty;
 }
 
-// Pulled flow populations and source pressures of a node of an interior
-// tile (offsets v3, see node_offsets).
+// Pulled flow populations of a node of an interior tile (offsets v3, see
+// node_offsets).
 template <bool NT>
-__device__ __forceinline__ void load_fp_tile(const float* tin, int rowe, const unsigned* v3, float* ft, float* ps) {
-#define PULL_FT(I)                                   \
-  ft[I] = pull_tile<I, kPF + I, NT>(tin, rowe, v3);  \
-  ps[I] = pull_tile<I, kPP, false>(tin, rowe, v3);
+__device__ __forceinline__ void load_fp_tile(const float* tin, int rowe, const unsigned* v3, float* ft) {
+#define PULL_FT(I) ft[I] = pull_tile<I, kPF + I, NT>(tin, rowe, v3);
   PULL_FT(0) PULL_FT(1) PULL_FT(2) PULL_FT(3) PULL_FT(4) PULL_FT(5) PULL_FT(6) PULL_FT(7) PULL_FT(8)
 #undef PULL_FT
 }
@@ -475,11 +465,8 @@ __device__ __forceinline__ float pull_wrap(const float* base, const unsigned* co
 }
 
 template <bool NT>
-__device__ __forceinline__ void load_fp_wrap(const float* base, const unsigned* col, const unsigned* row, float* ft,
-                                             float* ps) {
-#define PULL_FW(I)                                  \
-  ft[I] = pull_wrap<I, kPF + I, NT>(base, col, row); \
-  ps[I] = pull_wrap<I, kPP, false>(base, col, row);
+__device__ __forceinline__ void load_fp_wrap(const float* base, const unsigned* col, const unsigned* row, float* ft) {
+#define PULL_FW(I) ft[I] = pull_wrap<I, kPF + I, NT>(base, col, row);
   PULL_FW(0) PULL_FW(1) PULL_FW(2) PULL_FW(3) PULL_FW(4) PULL_FW(5) PULL_FW(6) PULL_FW(7) PULL_FW(8)
 #undef PULL_FW
 }
@@ -588,15 +575,15 @@ __device__ __forceinline__ void tile_impl(Lds<S>& s, const StepArgs& a, const Mo
   // the order parameter, so those loads are in flight through the first
   // barrier and the stencil stage: nothing waits for them before the ring's
   // velocities.
-  float ft[9], ps[9], h[9];
+  float ft[9], h[9];
   float j0 = 0.f, j1 = 0.f;
   // Only ring threads define these.  The others start from a kernel
   // argument, not a constant: with a constant there the compiler moves the
   // FP64 conversions of the ring values up to their loads, and the ring
   // threads then wait for those loads as soon as they are issued.
-  float rft[9], rps[9];
+  float rft[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) rft[i] = rps[i] = c.gx;
+  for (int i = 0; i < 9; ++i) rft[i] = c.gx;
   int ruy = 0, rux = 0;
   bool ring_ok = true;   // general path: the ring position is not beyond a wall
   // Stage A: phi tile with a 3-node halo (periodic wrap / even reflection at walls, Sec. IV)
@@ -619,7 +606,7 @@ __device__ __forceinline__ void tile_impl(Lds<S>& s, const StepArgs& a, const Mo
         ring_pos<S>(tid, ruy, rux);
         unsigned rv[3];
         node_offsets(g, x0, rux - 1, ruy - 1, rv);
-        load_fp_tile<false>(tin, g.rowe, rv, rft, rps);
+        load_fp_tile<false>(tin, g.rowe, rv, rft);
       }
     }
   } else {
@@ -646,9 +633,9 @@ __device__ __forceinline__ void tile_impl(Lds<S>& s, const StepArgs& a, const Mo
         if constexpr (WRAP) {
           unsigned rc[3], rr[3];
           wrap_offsets(g, rx, ry, rc, rr);
-          load_fp_wrap<false>(a.sin, rc, rr, rft, rps);
+          load_fp_wrap<false>(a.sin, rc, rr, rft);
         } else if (ring_ok) {
-          load_fp<WX, WY>(a, rx, ry, rft, rps);
+          load_fp<WX, WY>(a, rx, ry, rft);
         }
       }
     }
@@ -669,12 +656,12 @@ __device__ __forceinline__ void tile_impl(Lds<S>& s, const StepArgs& a, const Mo
   constexpr bool kEarlyH = kEarlyOwn;
   unsigned v3[3] = {0u, 0u, 0u};
   if constexpr (FAST) node_offsets(g, x0, lx, ty, v3);
-  if constexpr (kEarlyOwn) load_fp_tile<true>(tin, g.rowe, v3, ft, ps);
+  if constexpr (kEarlyOwn) load_fp_tile<true>(tin, g.rowe, v3, ft);
   if constexpr (!MOMENTS) {
     if (tid < S::NRING) {
       if (FAST || ring_ok) {
         NodeState rs;
-        velocity_from<FORM, false, S>(s, a, ruy, rux, rft, rps, rs);
+        velocity_from<FORM, false, S>(s, a, ruy, rux, rft, rs);
         const double ph = s.phi[ruy + 2][rux + 2];
         s.q[0][ruy][rux] = (float)(ph * rs.ux);
         s.q[1][ruy][rux] = (float)(ph * rs.uy);
@@ -687,10 +674,10 @@ __device__ __forceinline__ void tile_impl(Lds<S>& s, const StepArgs& a, const Mo
   if constexpr (WRAP) wrap_offsets(g, x, y, wc, wr);
   NodeState n;
   if (valid) {
-    if constexpr (WRAP) load_fp_wrap<true>(a.sin, wc, wr, ft, ps);
-    else if constexpr (!FAST) load_fp<WX, WY>(a, x, y, ft, ps);
-    else if constexpr (!kEarlyOwn) load_fp_tile<true>(tin, g.rowe, v3, ft, ps);
-    velocity_from<FORM, true, S>(s, a, uy_, ux_, ft, ps, n);
+    if constexpr (WRAP) load_fp_wrap<true>(a.sin, wc, wr, ft);
+    else if constexpr (!FAST) load_fp<WX, WY>(a, x, y, ft);
+    else if constexpr (!kEarlyOwn) load_fp_tile<true>(tin, g.rowe, v3, ft);
+    velocity_from<FORM, true, S>(s, a, uy_, ux_, ft, n);
     if constexpr (!MOMENTS) {
       const double ph = s.phi[uy_ + 2][ux_ + 2];
       s.q[0][uy_][ux_] = (float)(ph * n.ux);
@@ -796,11 +783,9 @@ __device__ __forceinline__ void tile_impl(Lds<S>& s, const StepArgs& a, const Mo
     if constexpr (DIRECT) {
       st_nt(at(tout + kPJ * 64, ob), (float)qx);
       st_nt(at(tout + (kPJ + 1) * 64, ob), (float)qy);
-      st_nt(at(tout + kPP * 64, ob), n.Pn);
     } else {
       a.sout[on + (unsigned)(kPJ * 64)] = (float)qx;
       a.sout[on + (unsigned)((kPJ + 1) * 64)] = (float)qy;
-      a.sout[on + (unsigned)(kPP * 64)] = n.Pn;
     }
 
     if (!(isfinite(n.ux) && isfinite(n.uy) && isfinite(phid))) atomicOr(a.status, 1);
@@ -821,9 +806,8 @@ __device__ __forceinline__ void tile_impl(Lds<S>& s, const StepArgs& a, const Mo
     // Flow collision, Eq. (29) with f^eq of Eq. (31) and F_i of Eq. (35)
     // (reading A1), factored per node.  With s_i = 3 c.u + 4.5 (c.u)^2 - 1.5 u^2,
     // F = F_sf + F_g and grad rho:
-    //   f_i^+ - w_i Pn = (1 - 1/tau_f) (f_i - w_i Pn)
-    //        + w_i [K0 + k c.F + s_i (K1 + k c.F + k c.grad(rho)/3)],
-    //   k = 1 - 1/(2 tau_f), K0 = (P - Pn)/tau_f - k u.F,
+    //   f_i^+ = (1 - 1/tau_f) f_i + w_i [K0 + k c.F + s_i (K1 + k c.F + k c.grad(rho)/3)],
+    //   k = 1 - 1/(2 tau_f), K0 = P/tau_f - k u.F,
     //   K1 = rho/(3 tau_f) - k u.F - k u.grad(rho)/3.
     // Directions come in opposite pairs (c_J = -c_I): s = e +- o with the
     // even part e = 4.5 (c.u)^2 - 1.5 u^2 and the odd part o = 3 c.u, so
@@ -832,7 +816,7 @@ __device__ __forceinline__ void tile_impl(Lds<S>& s, const StepArgs& a, const Mo
     // keep h + w (G0 +- 3 c.V).
     const double fx = (double)n.fx, fy = (double)n.fy, grx = (double)n.grx, gry = (double)n.gry;
     const double uF = n.ux * fx + n.uy * fy, uG = n.ux * grx + n.uy * gry;
-    const double K0 = omf * (n.P - (double)n.Pn) - cff * uF;
+    const double K0 = omf * n.P - cff * uF;
     const double K1 = omf * n.rho * (1.0 / 3.0) - cff * uF - cff * uG * (1.0 / 3.0);
     const double kFx = cff * fx, kFy = cff * fy;
     const double kFGx = kFx + cff * grx * (1.0 / 3.0), kFGy = kFy + cff * gry * (1.0 / 3.0);
