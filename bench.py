@@ -228,7 +228,7 @@ def bench_batched(steps, loop_steps):
             "looping_plain_lbm_step_MLUPS": round(loop, 1), "loop_steps": loop_steps,
             "speedup_vs_loop": round(batched / loop, 2), "unstable_instances": len(unstable),
             "unstable": unstable,
-            "launch_shape": {"one_kernel_per_form": bool(shape["split"]), "addressing": ("general", "interior", "wrapped")[shape["fast"]],
+            "launch_shape": {"one_kernel_per_form": bool(shape["split"]), "addressing": ("general", "interior + general", "wrapped")[shape["fast"]],
                              "workgroups_per_cu": shape["blocks_per_cu"] or "one per tile",
                              "tuned_ms_per_step": round(shape["ms_per_step"], 4),
                              "tile_shapes_per_size_class": classes},
@@ -443,7 +443,7 @@ def main():
                                f"mu1/mu2=100, sigma=1e-3, one run per force form in the paper's order",
                    "steps_per_form": dict(zip(FORMS, counts)),
                    "precision": "FP64 arithmetic (collision, stencils, forces) and FP64 phi; "
-                                "FP32 storage of f, h, (phi u) and P",
+                                "FP32 storage of f, h and (phi u)",
                    "storage_dtype": "fp32",
                    "step_bytes_per_node": BYTES_FUSED + BYTES_PHI,
                    "step_GBs": round((BYTES_FUSED + BYTES_PHI) * value * 1e6 / 1e9, 1)},

@@ -650,10 +650,10 @@ __device__ __forceinline__ void tile_impl(Lds<S>& s, const StepArgs& a, const Mo
   // forms, so their latency overlaps the ring's work (measured: no gain for
   // the CSF forms, and the stress forms need those registers for the ring).
   constexpr bool kEarlyOwn = FAST && FORM >= 2 && FORM <= 5;
-  // The same forms also request their h and (phi u) pulls before the last
-  // barrier (measured: CPF and PF -1 to -6 us; the stress and CSF forms
-  // would spill or slow down).
-  constexpr bool kEarlyH = kEarlyOwn;
+  // The CPF, PF and stress forms also request their h and (phi u) pulls
+  // before the last barrier (measured: -1 to -6 us; the CSF forms gain
+  // nothing).
+  constexpr bool kEarlyH = FAST && FORM <= 5;
   unsigned v3[3] = {0u, 0u, 0u};
   if constexpr (FAST) node_offsets(g, x0, lx, ty, v3);
   if constexpr (kEarlyOwn) load_fp_tile<true>(tin, g.rowe, v3, ft);
