@@ -160,13 +160,12 @@ int lbm_restore(lbm_sim* sim, const void* d_blob, void* stream);
  * segment without copies. */
 int lbm_step_blobs(lbm_sim* sim, const void* d_blob_in, void* d_blob_out, int32_t force_form, void* stream);
 
-/* Kernel timing with HIP events recorded on the launch stream: three per
- * timed step, before the fused kernel, between the two kernels and after the
- * order-parameter kernel.  period: 0 = off; k >= 1 = time the two launches of
- * every k-th step counted from this call, the first step after it included,
- * so k > 1 samples the launch durations with fewer events in the stream.
- * kernel: 0 = fused collide-stream kernel (first to second event), 1 = order
- * parameter kernel (second to third).  lbm_kernel_time
+/* Kernel timing with HIP events on the launch stream that take each timed
+ * kernel's own start and stop times from its dispatch (hipExtLaunchKernel:
+ * no packets between the kernels).  period: 0 = off; k >= 1 = time the two
+ * launches of every k-th step counted from this call, the first step after
+ * it included.  kernel: 0 = fused collide-stream kernel, 1 = order-parameter
+ * kernel.  lbm_kernel_time
  * synchronises and returns the summed elapsed milliseconds and the number of
  * timed launches since the last reset; every call of lbm_set_timing drains
  * the pending events and resets the counters.  LBM_E_INVAL for period < 0. */

@@ -169,12 +169,12 @@ struct lbm_sim {
   int64_t step;
   int timing;
   int64_t timing_base;   // step count when timing was last set: the first step after it is timed
-  // ring of event triples, one per timed step: before the fused kernel,
-  // between the two kernels (the fused kernel's stop and the order-parameter
-  // kernel's start), after the order-parameter kernel; a slot is drained
-  // (its elapsed times added) before reuse or on query
+  // ring of event quadruples, one per timed step: the fused kernel's start
+  // and stop, the order-parameter kernel's start and stop, each taken from
+  // the kernel's dispatch; a slot is drained (its elapsed times added) before
+  // reuse or on query
   static constexpr int kRing = 512;
-  hipEvent_t ev[kRing][3];
+  hipEvent_t ev[kRing][4];
   int ev_pending[kRing];
   int ev_next;
   double t_ms[2];
@@ -198,13 +198,13 @@ StepArgs step_args(const lbm_sim* s) {
   return a;
 }
 
-// Add the elapsed time of ring slot `j` of kernel `k` if it holds a launch.
+// Add the elapsed times of ring slot `j` (both kernels) if it holds a step.
 int drain_slot(lbm_sim* s, int j) {
   if (!s->ev_pending[j]) return LBM_OK;
-  HIPCHK(hipEventSynchronize(s->ev[j][2]));
+  HIPCHK(hipEventSynchronize(s->ev[j][3]));
   for (int k = 0; k < 2; ++k) {
     float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, s->ev[j][k], s->ev[j][k + 1]));
+    HIPCHK(hipEventElapsedTime(&ms, s->ev[j][2 * k], s->ev[j][2 * k + 1]));
     s->t_ms[k] += ms;
     s->t_n[k] += 1;
   }
@@ -218,17 +218,12 @@ int drain_all(lbm_sim* s) {
   return LBM_OK;
 }
 
-// Event e (0: before the fused kernel, 1: between the kernels, 2: after the
-// order-parameter kernel) of the timed step in slot j; e = 0 takes a new slot.
-int timer_mark(lbm_sim* s, int e, hipStream_t st, int* slot) {
-  if (e == 0) {
-    const int j = s->ev_next;
-    s->ev_next = (j + 1) % lbm_sim::kRing;
-    if (int r = drain_slot(s, j)) return r;
-    *slot = j;
-  }
-  HIPCHK(hipEventRecord(s->ev[*slot][e], st));
-  if (e == 2) s->ev_pending[*slot] = 1;
+// The next ring slot for a timed step (drained first).
+int timer_slot(lbm_sim* s, int* slot) {
+  const int j = s->ev_next;
+  s->ev_next = (j + 1) % lbm_sim::kRing;
+  if (int r = drain_slot(s, j)) return r;
+  *slot = j;
   return LBM_OK;
 }
 
@@ -321,16 +316,15 @@ int lbm_step(lbm_sim* s, int32_t nsteps, int32_t form, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   for (int32_t n = 0; n < nsteps; ++n) {
     StepArgs a = step_args(s);
-    int slot = 0;
     const bool timed = s->timing && (s->step - s->timing_base) % s->timing == 0;
+    int slot = -1;
     if (timed)
-      if (int r = timer_mark(s, 0, st, &slot)) return r;
-    HIPCHK(launch_fused(form, s->shape, a, st));
-    if (timed)
-      if (int r = timer_mark(s, 1, st, &slot)) return r;
-    HIPCHK(launch_phi(a.sout, s->phi(), s->phi(), s->L.g, s->c.wall_x, s->c.wall_y, s->shape, st));
-    if (timed)
-      if (int r = timer_mark(s, 2, st, &slot)) return r;
+      if (int r = timer_slot(s, &slot)) return r;
+    hipEvent_t* ev = slot >= 0 ? s->ev[slot] : nullptr;
+    HIPCHK(launch_fused(form, s->shape, a, st, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr));
+    HIPCHK(launch_phi(a.sout, s->phi(), s->phi(), s->L.g, s->c.wall_x, s->c.wall_y, s->shape, st,
+                      ev ? ev[2] : nullptr, ev ? ev[3] : nullptr));
+    if (slot >= 0) s->ev_pending[slot] = 1;
     s->cur = 1 - s->cur;
     s->step += 1;
   }
@@ -429,7 +423,7 @@ int lbm_set_timing(lbm_sim* s, int32_t enable) {
   if (enable < 0) return fail(LBM_E_INVAL, "timing period must be >= 0");
   if (enable && !s->ev[0][0]) {   // create the event ring on first use
     for (int j = 0; j < lbm_sim::kRing; ++j)
-      for (int e = 0; e < 3; ++e) HIPCHK(hipEventCreate(&s->ev[j][e]));
+      for (int e = 0; e < 4; ++e) HIPCHK(hipEventCreate(&s->ev[j][e]));
   }
   if (s->ev[0][0])
     if (int r = drain_all(s)) return r;
@@ -452,7 +446,7 @@ int lbm_kernel_time(lbm_sim* s, int32_t kernel, double* total_ms, int64_t* launc
 int lbm_destroy(lbm_sim* s) {
   if (!s) return LBM_OK;
   for (int j = 0; j < lbm_sim::kRing; ++j)
-    for (int e = 0; e < 3; ++e)
+    for (int e = 0; e < 4; ++e)
       if (s->ev[j][e]) (void)hipEventDestroy(s->ev[j][e]);
   delete s;
   return LBM_OK;

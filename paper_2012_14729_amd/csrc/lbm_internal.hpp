@@ -124,12 +124,15 @@ int sim_params(const lbm_sim* s, lbm_params* out);
 Phys sim_phys(const lbm_sim* s);
 int sim_view(const lbm_sim* s, SimView* v);
 
-// kernel launchers (lbm_kernels.hip); each returns the launch error code
-hipError_t launch_fused(int form, int shape, const StepArgs& a, hipStream_t s);
+// kernel launchers (lbm_kernels.hip); each returns the launch error code.
+// t0, t1 (both or neither): events that take the kernel's own start and stop
+// times from its dispatch.
+hipError_t launch_fused(int form, int shape, const StepArgs& a, hipStream_t s, hipEvent_t t0 = nullptr,
+                        hipEvent_t t1 = nullptr);
 hipError_t launch_moments(int form, const StepArgs& a, const MomentArgs& m, hipStream_t s);
 // phi_out = phi_in + d0 + sum of the pulled h (phi_out may be phi_in: in place)
 hipError_t launch_phi(const float* snew, const double* phi_in, double* phi_out, const Grid& g, int wall_x, int wall_y,
-                      int shape, hipStream_t s);
+                      int shape, hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 hipError_t launch_init(const float* phi0, const float* ux0, const float* uy0, float* s_tmp, float* s0, double* phi,
                        const Grid& g, const Phys& c, hipStream_t s);
 // sum of the phi plane: at most npartial (and one per 256 nodes) partial sums, then one

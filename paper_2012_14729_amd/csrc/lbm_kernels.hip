@@ -15,6 +15,8 @@
 // HBM; everything with a wider footprint comes from LDS.  The state arrays
 // interleave their 20 planes in 64-node row segments (lbm_internal.hpp), so a
 // wavefront's loads and stores of one row segment form one contiguous run.
+#include <hip/hip_ext.h>
+
 #include "lbm_tile.hpp"
 
 namespace pflbm {
@@ -178,78 +180,89 @@ dim3 tile_grid(const Grid& g) {
   return dim3((ntiles + kXcds - 1) / kXcds * kXcds);
 }
 
+// A launch whose start and stop times events t0/t1 take from the dispatch
+// itself when given (timed steps), else a plain launch.
+#define PFLBM_LAUNCH(K, GRID, BLOCK, ST, T0, T1, ...)                         \
+  do {                                                                        \
+    if (T0) hipExtLaunchKernelGGL(K, GRID, BLOCK, 0, ST, T0, T1, 0, __VA_ARGS__); \
+    else hipLaunchKernelGGL(K, GRID, BLOCK, 0, ST, __VA_ARGS__);              \
+  } while (0)
+
 template <class S, int FORM, int BC>
-hipError_t launch_fused_t(const StepArgs& a, const MomentArgs& m, bool moments, hipStream_t st) {
+hipError_t launch_fused_t(const StepArgs& a, const MomentArgs& m, bool moments, hipStream_t st, hipEvent_t t0,
+                          hipEvent_t t1) {
   if (moments) hipLaunchKernelGGL((k_fused<S, FORM, true, BC>), tile_grid<S>(a.g), dim3(S::NT), 0, st, a, m);
-  else hipLaunchKernelGGL((k_fused<S, FORM, false, BC>), tile_grid<S>(a.g), dim3(S::NT), 0, st, a, m);
+  else PFLBM_LAUNCH((k_fused<S, FORM, false, BC>), tile_grid<S>(a.g), dim3(S::NT), st, t0, t1, a, m);
   return hipGetLastError();
 }
 
 // Single lattices: every boundary set-up in shape 0; periodic lattices also
 // in the other shapes (step only; the moments run in shape 0).
 template <int FORM>
-hipError_t launch_form(int shape, const StepArgs& a, const MomentArgs& m, bool moments, hipStream_t st) {
+hipError_t launch_form(int shape, const StepArgs& a, const MomentArgs& m, bool moments, hipStream_t st, hipEvent_t t0,
+                       hipEvent_t t1) {
   const int bc = a.c.wall_x | (a.c.wall_y << 1);
   if (!moments && bc == 0) {
     switch (shape) {
-      case 1: return launch_fused_t<S1, FORM, 0>(a, m, false, st);
-      case 2: return launch_fused_t<S2, FORM, 0>(a, m, false, st);
-      case 3: return launch_fused_t<S3, FORM, 0>(a, m, false, st);
+      case 1: return launch_fused_t<S1, FORM, 0>(a, m, false, st, t0, t1);
+      case 2: return launch_fused_t<S2, FORM, 0>(a, m, false, st, t0, t1);
+      case 3: return launch_fused_t<S3, FORM, 0>(a, m, false, st, t0, t1);
       default: break;
     }
   }
   switch (bc) {
-    case 0: return launch_fused_t<S0, FORM, 0>(a, m, moments, st);
-    case 1: return launch_fused_t<S0, FORM, 1>(a, m, moments, st);
-    case 2: return launch_fused_t<S0, FORM, 2>(a, m, moments, st);
-    default: return launch_fused_t<S0, FORM, 3>(a, m, moments, st);
+    case 0: return launch_fused_t<S0, FORM, 0>(a, m, moments, st, t0, t1);
+    case 1: return launch_fused_t<S0, FORM, 1>(a, m, moments, st, t0, t1);
+    case 2: return launch_fused_t<S0, FORM, 2>(a, m, moments, st, t0, t1);
+    default: return launch_fused_t<S0, FORM, 3>(a, m, moments, st, t0, t1);
   }
 }
 
-hipError_t dispatch(int form, int shape, const StepArgs& a, const MomentArgs& m, bool moments, hipStream_t st) {
+hipError_t dispatch(int form, int shape, const StepArgs& a, const MomentArgs& m, bool moments, hipStream_t st,
+                    hipEvent_t t0, hipEvent_t t1) {
   switch (form) {
-    case 0: return launch_form<0>(shape, a, m, moments, st);
-    case 1: return launch_form<1>(shape, a, m, moments, st);
-    case 2: return launch_form<2>(shape, a, m, moments, st);
-    case 3: return launch_form<3>(shape, a, m, moments, st);
-    case 4: return launch_form<4>(shape, a, m, moments, st);
-    case 5: return launch_form<5>(shape, a, m, moments, st);
-    case 6: return launch_form<6>(shape, a, m, moments, st);
-    case 7: return launch_form<7>(shape, a, m, moments, st);
+    case 0: return launch_form<0>(shape, a, m, moments, st, t0, t1);
+    case 1: return launch_form<1>(shape, a, m, moments, st, t0, t1);
+    case 2: return launch_form<2>(shape, a, m, moments, st, t0, t1);
+    case 3: return launch_form<3>(shape, a, m, moments, st, t0, t1);
+    case 4: return launch_form<4>(shape, a, m, moments, st, t0, t1);
+    case 5: return launch_form<5>(shape, a, m, moments, st, t0, t1);
+    case 6: return launch_form<6>(shape, a, m, moments, st, t0, t1);
+    case 7: return launch_form<7>(shape, a, m, moments, st, t0, t1);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <class S>
 hipError_t launch_phi_t(const float* snew, const double* phi_in, double* phi_out, const Grid& g, int bc,
-                        hipStream_t s) {
+                        hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
   switch (bc) {
-    case 0: hipLaunchKernelGGL((k_phi<S, 0>), tile_grid<S>(g), dim3(S::NT), 0, s, snew, phi_in, phi_out, g); break;
-    case 1: hipLaunchKernelGGL((k_phi<S, 1>), tile_grid<S>(g), dim3(S::NT), 0, s, snew, phi_in, phi_out, g); break;
-    case 2: hipLaunchKernelGGL((k_phi<S, 2>), tile_grid<S>(g), dim3(S::NT), 0, s, snew, phi_in, phi_out, g); break;
-    default: hipLaunchKernelGGL((k_phi<S, 3>), tile_grid<S>(g), dim3(S::NT), 0, s, snew, phi_in, phi_out, g); break;
+    case 0: PFLBM_LAUNCH((k_phi<S, 0>), tile_grid<S>(g), dim3(S::NT), s, t0, t1, snew, phi_in, phi_out, g); break;
+    case 1: PFLBM_LAUNCH((k_phi<S, 1>), tile_grid<S>(g), dim3(S::NT), s, t0, t1, snew, phi_in, phi_out, g); break;
+    case 2: PFLBM_LAUNCH((k_phi<S, 2>), tile_grid<S>(g), dim3(S::NT), s, t0, t1, snew, phi_in, phi_out, g); break;
+    default: PFLBM_LAUNCH((k_phi<S, 3>), tile_grid<S>(g), dim3(S::NT), s, t0, t1, snew, phi_in, phi_out, g); break;
   }
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_fused(int form, int shape, const StepArgs& a, hipStream_t s) {
-  return dispatch(form, shape, a, MomentArgs{}, false, s);
+hipError_t launch_fused(int form, int shape, const StepArgs& a, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+  return dispatch(form, shape, a, MomentArgs{}, false, s, t0, t1);
 }
 
 hipError_t launch_moments(int form, const StepArgs& a, const MomentArgs& m, hipStream_t s) {
-  return dispatch(form, 0, a, m, true, s);
+  return dispatch(form, 0, a, m, true, s, nullptr, nullptr);
 }
 
 hipError_t launch_phi(const float* snew, const double* phi_in, double* phi_out, const Grid& g, int wall_x, int wall_y,
-                      int shape, hipStream_t s) {
+                      int shape, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
   const int bc = wall_x | (wall_y << 1);
   switch (shape) {
-    case 1: return launch_phi_t<S1>(snew, phi_in, phi_out, g, bc, s);
-    case 2: return launch_phi_t<S2>(snew, phi_in, phi_out, g, bc, s);
-    case 3: return launch_phi_t<S3>(snew, phi_in, phi_out, g, bc, s);
-    default: return launch_phi_t<S0>(snew, phi_in, phi_out, g, bc, s);
+    case 1: return launch_phi_t<S1>(snew, phi_in, phi_out, g, bc, s, t0, t1);
+    case 2: return launch_phi_t<S2>(snew, phi_in, phi_out, g, bc, s, t0, t1);
+    case 3: return launch_phi_t<S3>(snew, phi_in, phi_out, g, bc, s, t0, t1);
+    default: return launch_phi_t<S0>(snew, phi_in, phi_out, g, bc, s, t0, t1);
   }
 }
 
