@@ -72,9 +72,9 @@ __device__ __forceinline__ void band(int t0, int t1, int& first, int& end, int& 
 // Addressing paths of a batched step kernel: every tile general (0);
 // interior tiles on the interior path, the others general (1); every tile
 // wrapped (2, when every instance's arrays allow it).  One kernel holds at
-// most two paths: the compiler merges the interior or general body with the
-// wrapped one into a single body that needs more registers than four waves
-// per SIMD allow (spills).
+// most two paths: the compiler merges the bodies of a kernel into shared
+// blocks, and a kernel with the interior and the wrapped body measured no
+// faster than either path alone.
 constexpr int kBatchGeneral = 0, kBatchInterior = 1, kBatchWrapped = 2;
 
 template <class S, int FORM, int PATHS>
