@@ -140,7 +140,7 @@ int lbm_status(lbm_sim* sim, int32_t* diverged, void* stream);
 /* Number of completed time steps since init (host counter). */
 int lbm_get_step(const lbm_sim* sim, int64_t* step);
 
-/* Checkpoint: the complete device state (populations, pressure, FP64 order
+/* Checkpoint: the complete device state (populations, FP64 order
  * parameter, (phi u) history, divergence flag) copied to/from a caller-owned
  * device blob of lbm_state_bytes bytes; the blob's unused tail is written as
  * zeros, so equal states give equal blobs.  Restoring and stepping
@@ -165,7 +165,7 @@ int lbm_step_blobs(lbm_sim* sim, const void* d_blob_in, void* d_blob_out, int32_
  * no packets between the kernels).  period: 0 = off; k >= 1 = time the two
  * launches of every k-th step counted from this call, the first step after
  * it included.  kernel: 0 = fused collide-stream kernel, 1 = order-parameter
- * kernel.  lbm_kernel_time
+ * kernel.  Not for steps captured into a HIP graph.  lbm_kernel_time
  * synchronises and returns the summed elapsed milliseconds and the number of
  * timed launches since the last reset; every call of lbm_set_timing drains
  * the pending events and resets the counters.  LBM_E_INVAL for period < 0. */
