@@ -107,6 +107,28 @@ def test_zero_steps_and_timing():
     assert s.kernel_time(0)[1] == 1
 
 
+def test_kernel_times_fit_inside_the_wall_clock():
+    """The timed kernels' events take each kernel's own dispatch start and
+    stop: over 24 timed steps of a 1024x1024 droplet the two kernels' summed
+    times lie inside the wall-clock time of those steps and cover most of it
+    (a broken pair of events would read zero or span the whole queue)."""
+    import time
+    p, phi0, _, _ = WL.config_droplet_large(1024)
+    s = sim_of(p, np.asarray(phi0, np.float32))
+    s.step(4, "cpf2")
+    torch.cuda.synchronize()
+    s.set_timing(True, period=1)
+    t0 = time.perf_counter()
+    s.step(24, "cpf2")
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    (f_ms, f_n), (p_ms, p_n) = s.kernel_time(0), s.kernel_time(1)
+    print(f"[timing] wall {wall_ms:.3f} ms, fused {f_ms:.3f} ms / {f_n}, phi {p_ms:.3f} ms / {p_n}", flush=True)
+    assert f_n == 24 and p_n == 24
+    assert 0.0 < p_ms < f_ms
+    assert 0.5 * wall_ms < f_ms + p_ms <= wall_ms
+
+
 def _one_step_full_size(p, phi0, form):
     op = R.Params(**{k: (None if k == "rho0" and math.isnan(v) else v) for k, v in p.as_dict().items()})
     phi32 = np.asarray(phi0, np.float32)
