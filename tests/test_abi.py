@@ -67,6 +67,18 @@ def test_invalid_params_rejected(bad):
     assert _lib.lib().lbm_last_error()
 
 
+def test_grid_size_limit_of_32_bit_indices():
+    """A state array of 20 FP32 planes is indexed with 32-bit element
+    offsets: 20 * (nx rounded up to 64) * ny must stay below 2^32."""
+    ny_max = (2 ** 32 - 1) // (20 * 16384)          # the largest ny for nx = 16384
+    code, n = ws_bytes(good(nx=16384, ny=ny_max))
+    assert code == 0 and n >= 16384 * ny_max * (2 * 20 * 4 + 8)
+    code, _ = ws_bytes(good(nx=16384, ny=ny_max + 1))
+    assert code == _lib.LBM_E_INVAL and b"2^32" in _lib.lib().lbm_last_error()
+    code, _ = ws_bytes(good(nx=16384 - 63, ny=ny_max + 1))   # nx is padded to 64 first
+    assert code == _lib.LBM_E_INVAL
+
+
 @pytest.mark.parametrize("ok", [dict(wall_x=2), dict(wall_y=2), dict(wall_x=2, wall_y=2), dict(wall_x=2, wall_y=1),
                                 dict(wall_y=1, u_wall_lo=-0.01, u_wall_hi=0.01)])
 def test_wall_kinds_accepted(ok):
