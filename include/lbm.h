@@ -62,9 +62,9 @@ enum lbm_status_code {
 };
 
 /* Problem statement in lattice units (Sec. II.A, Sec. III, Sec. IV).
- * Validation (LBM_E_INVAL): nx, ny >= 8; 20 * (nx rounded up to 64) * ny
- * < 2^32 (32-bit element indices: about 14600^2 nodes at most); wall_x,
- * wall_y in {0, 1, 2}; at
+ * Validation (LBM_E_INVAL): nx, ny >= 8; (nx rounded up to 64) * ny < 2^31
+ * (a lattice needs about 168 B per node, so 288 GB of HBM hold about 1.7e9
+ * nodes, 41000^2); wall_x, wall_y in {0, 1, 2}; at
  * most one walled axis may have moving walls, and free-slip walls do not
  * move; rho1, rho2 > 0; nu1, nu2 > 0 (so
  * tau_f = 1/2 + 3 nu > 1/2 everywhere); sigma >= 0; W > 0; M >= 0;

@@ -51,8 +51,8 @@ bool finite(double v) { return std::isfinite(v); }
 int validate(const lbm_params* p) {
   if (!p) return fail(LBM_E_INVAL, "params is NULL");
   if (p->nx < 8 || p->ny < 8) return fail(LBM_E_INVAL, "nx, ny must be >= 8 (got %d, %d)", p->nx, p->ny);
-  if ((long long)kNPL * (((long long)p->nx + 63) / 64 * 64) * p->ny >= (1LL << 32))
-    return fail(LBM_E_INVAL, "grid too large (a %d-plane state array must hold fewer than 2^32 elements)", kNPL);
+  if ((((long long)p->nx + 63) / 64 * 64) * p->ny >= (1LL << 31))
+    return fail(LBM_E_INVAL, "grid too large (the padded plane must hold fewer than 2^31 nodes)");
   if (p->wall_x < 0 || p->wall_x > 2 || p->wall_y < 0 || p->wall_y > 2)
     return fail(LBM_E_INVAL, "wall_x, wall_y must be 0 (periodic), 1 (no-slip) or 2 (free-slip)");
   if (p->wall_x && p->wall_y && (p->u_wall_lo != 0.0 || p->u_wall_hi != 0.0))

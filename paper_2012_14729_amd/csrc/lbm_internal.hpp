@@ -78,10 +78,12 @@ __host__ __device__ constexpr int fast_bits(long long plane_nodes) {
   return kFastInterior | ((long long)kNPL * plane_nodes * 4 <= 0xffffffffLL ? kFastWrap : 0);
 }
 
-// Element index of plane 0 of node (x, y) in a state array (20 ps < 2^32 is
-// validated); plane p of the node is 64 p elements further.
-__host__ __device__ __forceinline__ unsigned nbase(const Grid& g, int x, int y) {
-  return (unsigned)(y * g.ncx + (x >> 6)) * (unsigned)kSegE + (unsigned)(x & 63);
+// Element index of plane 0 of node (x, y) in a state array, 64-bit (a state
+// array may hold more than 2^32 elements; the segment index y ncx + x / 64
+// stays below 2^31 because ps < 2^31 is validated); plane p of the node is
+// 64 p elements further.
+__host__ __device__ __forceinline__ size_t nbase(const Grid& g, int x, int y) {
+  return (size_t)(unsigned)(y * g.ncx + (x >> 6)) * (size_t)kSegE + (size_t)(x & 63);
 }
 
 struct StepArgs {

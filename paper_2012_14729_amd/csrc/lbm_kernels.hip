@@ -47,7 +47,7 @@ __global__ __launch_bounds__(256) void k_init_local(const float* __restrict__ ph
   const int x = blockIdx.x * 64 + (threadIdx.x & 63);
   const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (x >= g.pitch || y >= g.ny) return;
-  const unsigned on = nbase(g, x, y);
+  const size_t on = nbase(g, x, y);
   if (x >= g.nx) {
     // lanes past nx in the last 64-node segment of a row: no step writes
     // them, so they are zeroed here (equal states then save to equal blobs)
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(256) void k_init_unstream(const float* __restrict__
   const int x = blockIdx.x * 64 + (threadIdx.x & 63);
   const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (x >= g.nx || y >= g.ny) return;
-  const unsigned on = nbase(g, x, y);
+  const size_t on = nbase(g, x, y);
 #pragma unroll
   for (int j = 0; j < 9; ++j) {
     // the node that pulls this slot at the first step, and in which direction
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void k_init_unstream(const float* __restrict__
     bool out_x = false, out_y = false;
     if (wx) out_x = (tx < 0) | (tx >= g.nx); else tx = (tx + g.nx) % g.nx;
     if (wy) out_y = (ty < 0) | (ty >= g.ny); else ty = (ty + g.ny) % g.ny;
-    unsigned src;
+    size_t src;
     int slot;
     if (!out_x && !out_y) { src = nbase(g, tx, ty); slot = j; }
     else if (out_x && !out_y && g.slip_x) { src = nbase(g, x, ty); slot = mirror_x(j); }

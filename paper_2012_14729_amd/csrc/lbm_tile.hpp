@@ -65,7 +65,7 @@ __device__ __forceinline__ int halo_coord(int c, int n) {
 // element index of plane 0 of the source node in a state array; `slot` is
 // the direction to read there.
 template <int I>
-__device__ __forceinline__ unsigned src_base(int x, int y, const Grid& g, int wx, int wy, int& slot) {
+__device__ __forceinline__ size_t src_base(int x, int y, const Grid& g, int wx, int wy, int& slot) {
   int sx = x - cx(I), sy = y - cy(I);
   bool out_x = false, out_y = false;
   if (cx(I) != 0) {
@@ -309,7 +309,7 @@ __device__ __forceinline__ void load_fp(const StepArgs& a, int x, int y, float* 
 #define PULL_FP(I)                                               \
   {                                                              \
     int sl_;                                                     \
-    const unsigned b_ = src_base<I>(x, y, a.g, wx, wy, sl_);     \
+    const size_t b_ = src_base<I>(x, y, a.g, wx, wy, sl_);       \
     ft[I] = a.sin[b_ + (unsigned)((kPF + sl_) * 64)];            \
   }
   PULL_FP(0) PULL_FP(1) PULL_FP(2) PULL_FP(3) PULL_FP(4) PULL_FP(5) PULL_FP(6) PULL_FP(7) PULL_FP(8)
@@ -494,7 +494,7 @@ __device__ __forceinline__ bool wall_hit(int x, int y, const Grid& g, const Phys
 // sets, stored with the wall term applied (general tiles) or directly
 // (interior and wrapped tiles: output origin tout, byte offset ob).
 template <int I, bool DIRECT, bool WX, bool WY>
-__device__ __forceinline__ void store_pair(const StepArgs& a, int x, int y, unsigned on, float* tout, unsigned ob,
+__device__ __forceinline__ void store_pair(const StepArgs& a, int x, int y, size_t on, float* tout, unsigned ob,
                                            double fpi, double fpj, double hpi, double hpj, double rho, double phid,
                                            double& d0sum) {
   constexpr int J = opp(I);
@@ -567,7 +567,7 @@ __device__ __forceinline__ void tile_impl(Lds<S>& s, const StepArgs& a, const Mo
     act = (x0 + lx < g.nx) && (y0 + ty < g.ny);
     if constexpr (WRAP) tout = a.sout;   // wrapped offsets are from the array base
   }
-  const unsigned on = nbase(g, x, y);   // general path: plane 0 of this node (valid nodes)
+  const size_t on = nbase(g, x, y);   // general path: plane 0 of this node (valid nodes)
 
   // This node's flow populations are pulled after the ring velocities (the
   // ring threads would otherwise hold both sets of registers at once).  The
@@ -747,7 +747,7 @@ __device__ __forceinline__ void tile_impl(Lds<S>& s, const StepArgs& a, const Mo
 #define PULL_HG(I)                                                 \
   {                                                                \
     int sl_;                                                       \
-    const unsigned b_ = src_base<I>(x, y, g, wx, wy, sl_);         \
+    const size_t b_ = src_base<I>(x, y, g, wx, wy, sl_);           \
     h[I] = a.sin[b_ + (unsigned)((kPH + sl_) * 64)];               \
   }
       PULL_HG(1) PULL_HG(2) PULL_HG(3) PULL_HG(4) PULL_HG(5) PULL_HG(6) PULL_HG(7) PULL_HG(8)
@@ -928,7 +928,7 @@ __device__ __forceinline__ void phi_tile_impl(const float* __restrict__ snew, co
 #define PULL_PH(I)                                               \
   {                                                              \
     int sl_;                                                     \
-    const unsigned b_ = src_base<I>(x, y, g, wx, wy, sl_);       \
+    const size_t b_ = src_base<I>(x, y, g, wx, wy, sl_);         \
     sum += (double)snew[b_ + (unsigned)((kPH + sl_) * 64)];      \
   }
     PULL_PH(1) PULL_PH(2) PULL_PH(3) PULL_PH(4) PULL_PH(5) PULL_PH(6) PULL_PH(7) PULL_PH(8)

@@ -67,15 +67,17 @@ def test_invalid_params_rejected(bad):
     assert _lib.lib().lbm_last_error()
 
 
-def test_grid_size_limit_of_32_bit_indices():
-    """A state array of 20 FP32 planes is indexed with 32-bit element
-    offsets: 20 * (nx rounded up to 64) * ny must stay below 2^32."""
-    ny_max = (2 ** 32 - 1) // (20 * 16384)          # the largest ny for nx = 16384
-    code, n = ws_bytes(good(nx=16384, ny=ny_max))
-    assert code == 0 and n >= 16384 * ny_max * (2 * 20 * 4 + 8)
-    code, _ = ws_bytes(good(nx=16384, ny=ny_max + 1))
-    assert code == _lib.LBM_E_INVAL and b"2^32" in _lib.lib().lbm_last_error()
-    code, _ = ws_bytes(good(nx=16384 - 63, ny=ny_max + 1))   # nx is padded to 64 first
+def test_grid_size_limit():
+    """State arrays are indexed with 64-bit element offsets, so a lattice
+    may exceed 2^32 elements per state array; the padded plane (nx rounded
+    up to 64, times ny) must stay below 2^31 nodes."""
+    code, n = ws_bytes(good(nx=16384, ny=16384))         # 20 * 2^28 elements per state array
+    assert code == 0 and n >= 16384 * 16384 * (2 * 20 * 4 + 8)
+    ny_max = (2 ** 31 - 1) // 65536
+    assert ws_bytes(good(nx=65536, ny=ny_max))[0] == 0
+    code, _ = ws_bytes(good(nx=65536, ny=ny_max + 1))
+    assert code == _lib.LBM_E_INVAL and b"2^31" in _lib.lib().lbm_last_error()
+    code, _ = ws_bytes(good(nx=65536 - 63, ny=ny_max + 1))   # nx is padded to 64 first
     assert code == _lib.LBM_E_INVAL
 
 

@@ -129,6 +129,40 @@ def test_kernel_times_fit_inside_the_wall_clock():
     assert 0.5 * wall_ms < f_ms + p_ms <= wall_ms
 
 
+def test_lattice_past_32_bit_element_offsets():
+    """A 16384 x 13312 periodic lattice: a state array (20 FP32 planes) holds
+    4.36e9 > 2^32 elements, so the upper rows' offsets need 64 bits.  phi0
+    tiles a 1024 x 832 droplet field 16 x 16 times; a periodic lattice is
+    translation invariant and every addressing path gives the same bits, so
+    after 3 steps each 1024 x 832 block equals the small lattice's fields
+    exactly.  Checked: the four corner blocks (the top ones lie past element
+    2^32 of the state arrays)."""
+    import dataclasses
+    bx, by, reps, form = 1024, 832, 16, "cpf2"
+    p_small = WL.ParamSet(nx=bx, ny=by, rho1=1000.0, rho2=1.0, nu1=1.0 / 30.0, nu2=1.0 / 3.0, sigma=1e-3, W=5.0,
+                          M=0.1, tau_h=0.8)
+    phi_s = np.asarray(WL.droplet(bx, by, 128.0, 5.0), np.float32)
+    small = sim_of(p_small, phi_s)
+    small.step(3, form)
+    ms = small.moments(form)
+    p_big = dataclasses.replace(p_small, nx=bx * reps, ny=by * reps)
+    assert 20 * p_big.nx * p_big.ny > 2 ** 32
+    print(f"[big] {p_big.nx}x{p_big.ny}: init", flush=True)
+    big = sim_of(p_big, np.tile(phi_s, (reps, reps)))
+    big.step(3, form)
+    keys = ("phi", "ux", "uy")
+    out = {k: torch.empty((p_big.ny, p_big.nx), dtype=torch.float32, device=ms["phi"].device) for k in keys}
+    mb = big.moments(form, out=out)
+    torch.cuda.synchronize()
+    assert not big.status()
+    for j in (0, reps - 1):
+        for i in (0, reps - 1):
+            for k in keys:
+                blk = mb[k][j * by:(j + 1) * by, i * bx:(i + 1) * bx]
+                assert torch.equal(blk, ms[k]), (j, i, k)
+    print(f"[big] corner blocks equal the {bx}x{by} lattice", flush=True)
+
+
 def _one_step_full_size(p, phi0, form):
     op = R.Params(**{k: (None if k == "rho0" and math.isnan(v) else v) for k, v in p.as_dict().items()})
     phi32 = np.asarray(phi0, np.float32)
