@@ -378,19 +378,24 @@ def main():
     torch.cuda.synchronize()
     print("[bench] warm-up done", file=sys.stderr, flush=True)
 
-    # The launch durations are sampled on one step in `period` of each run,
-    # its first step included: events around every launch would add their
-    # own gaps to the timed region.  A run's first step is slower than the
-    # rest (the previous run's state, not this one's, sits in the caches),
-    # so a period no longer than the shortest run also samples later steps.
+    # The launch durations are sampled on one step in `period` of each run:
+    # timing every launch costs the timed region about 5 %.  A run's first
+    # step is slower than the rest (the previous run's state, not this one's,
+    # sits in the caches), so the sample is stratified: run j starts sampling
+    # at its step j mod period, and every step index mod period is sampled
+    # equally often over the runs, the first steps at their own frequency.
     timed = [(f, sims[f], n) for f, n in zip(FORMS, counts) if n > 0]
     period = min([TIMING_PERIOD] + [n for _, _, n in timed])
-    for _, s, _ in timed:
+    for _, s, _ in timed:   # create the event rings outside the timed region
         s.set_timing(True, period=period)
+        s.set_timing(False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for f, s, n in timed:
-        for _ in range(n):
+    for j, (f, s, n) in enumerate(timed):
+        lead = j % period
+        for i in range(n):
+            if i == lead:
+                s.set_timing(True, period=period)   # no events pending: no synchronisation
             s.step(1, f)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
