@@ -42,8 +42,17 @@ CASES = {
 @pytest.mark.parametrize("case", sorted(CASES))
 @pytest.mark.parametrize("form", ["stf1", "stf2", "cpf1", "cpf2", "pf1", "pf2", "csf1", "csf2"])
 def test_one_adjoint_step_matches_oracle_vjp(case, form):
+    check_one_adjoint_step(*CASES[case](), case, form)
+
+
+def test_full_size_adjoint_step_matches_oracle_vjp():
+    """One adjoint step on the benchmark's sheared drop (512 x 256, walls at
+    +-U, STF-2), the size and form the benchmark's adjoint leg runs."""
+    check_one_adjoint_step(*WL.config_shear(), "shear_512x256", "stf2")
+
+
+def check_one_adjoint_step(p, phi0, ux0, uy0, case, form):
     import paper_2012_14729_amd as P
-    p, phi0, ux0, uy0 = CASES[case]()
     k = 4
     op = oracle_params(p)
     sig = torch.tensor(op.sigma, requires_grad=True)

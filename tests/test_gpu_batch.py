@@ -156,3 +156,46 @@ def test_every_tile_shape_matches_single_lattice(shape, cfg, monkeypatch):
         ms, mb = s.moments(P.FORMS[f]), b.moments(k)
         for key in ("phi", "rho", "ux", "uy", "P"):
             assert torch.equal(ms[key], mb[key]), (shape, cfg, k, key)
+
+
+def test_full_size_batch_sampled_instances():
+    """The benchmark's batch (512 instances, sides 32-512, seed 14729, 48.7 M
+    nodes) in the launch shape the tuner picks, as the benchmark runs it:
+    sampled instances (the smallest, the largest, ragged sides, every force
+    form) equal single-lattice runs bit for bit after 40 steps, and the
+    smallest sampled instance matches the oracle within the parity bar."""
+    import paper_2012_14729_amd as P
+    insts = WL.batch_instances(512, seed=14729)
+    params = [p for p, _, _ in insts]
+    forms = [f for _, f, _ in insts]
+    phis = [np.asarray(x, np.float32) for _, _, x in insts]
+    b = P.Batch([p.as_dict() for p in params], forms, phis)
+    print(f"[full batch] launch shape {b.config}", flush=True)
+    steps = 40
+    b.step(steps)
+    torch.cuda.synchronize()
+    sides = [p.nx for p in params]
+    pick = {sides.index(min(sides)), sides.index(max(sides))}
+    for f in range(8):   # one instance of each form, ragged sides first
+        ks = [k for k in range(512) if forms[k] == f and sides[k] % 64 and k not in pick]
+        pick.add(ks[0] if ks else forms.index(f))
+    for k in sorted(pick):
+        p, f, phi = params[k], forms[k], phis[k]
+        s = P.Simulation(p.as_dict(), phi)
+        s.step(steps, P.FORMS[f])
+        ms, mb = s.moments(P.FORMS[f]), b.moments(k)
+        for key in ("phi", "rho", "ux", "uy", "P"):
+            assert torch.equal(ms[key], mb[key]), (k, p.nx, key)
+        assert b.status()[k] == s.status()
+    k = min(pick, key=lambda i: sides[i])
+    p, f, phi = params[k], forms[k], phis[k]
+    op = R.Params(**{kk: (None if kk == "rho0" else v) for kk, v in p.as_dict().items()})
+    st = R.run(R.init(op, torch.tensor(phi, dtype=torch.float64)), R.FORMS[f], op, steps)
+    ref = {kk: v.numpy() for kk, v in R.moments(st, R.FORMS[f], op).items()}
+    got = {kk: v.cpu().numpy().astype(np.float64) for kk, v in b.moments(k).items()}
+    umax = np.sqrt(ref["ux"] ** 2 + ref["uy"] ** 2).max()
+    eu = max(np.abs(got["ux"] - ref["ux"]).max(), np.abs(got["uy"] - ref["uy"]).max()) / umax
+    ephi = np.abs(got["phi"] - ref["phi"]).max()
+    print(f"[full batch] {len(pick)} sampled instances bitwise; instance {k} ({p.nx}^2, {R.FORMS[f]}) vs oracle: "
+          f"e_phi {ephi:.2e} e_u {eu:.2e}", flush=True)
+    assert ephi < 1e-5 and eu < 1e-5
